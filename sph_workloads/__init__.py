@@ -1,0 +1,236 @@
+"""Seeded synthetic workloads for the WCSPH hot path.
+
+This module only generates inputs: particle positions, velocities, masses,
+types and ids, plus the run parameters that describe each workload.  It holds
+none of the method's arithmetic (no kernels, neighbour search, density,
+equation of state, momentum or time stepping), so both the GPU path and the
+CPU oracle can take their inputs from it.
+
+Workloads (the paper's Taylor-Green section and dam-break example describe the
+geometries; the sizes are the benchmark's):
+
+  tg64        2D Taylor-Green vortex, 64x64 lattice, periodic unit box
+  tg512       2D Taylor-Green vortex, 512x512 lattice jittered by +-0.1 dx
+  tg256       2D Taylor-Green vortex, 256x256 lattice (adjoint workload)
+  tg32        2D Taylor-Green vortex, 32x32 lattice (adjoint oracle companion)
+  dambreak3d  3D column of water (0.4 x 0.4 x 0.8) in a 1.6 x 0.67 x 0.6 tank
+              with three layers of wall particles, gravity -9.81
+  cube256     3D periodic cube, 256^3 lattice jittered by +-0.2 dx, Gaussian
+              random velocities with standard deviation 0.1
+
+Array layout is SoA: x, u have shape (dim, n) float64; m (n,) float64;
+ptype (n,) uint8 (0 fluid, 1 wall); pid (n,) int32.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Tuple
+
+import numpy as np
+
+CUBIC = 0
+WENDLAND = 1
+FLUID = 0
+WALL = 1
+
+
+@dataclasses.dataclass
+class Params:
+    dim: int
+    kernel: int            # CUBIC or WENDLAND
+    h: float               # smoothing length (support radius 2h)
+    rho0: float
+    c0: float
+    nu: float
+    eta: float
+    dt: float
+    g: Tuple[float, float, float]
+    lo: Tuple[float, float, float]
+    hi: Tuple[float, float, float]
+    periodic: Tuple[int, int, int]
+    cell_div: int = 1      # cells per support radius along an axis
+
+    def replace(self, **kw) -> "Params":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclasses.dataclass
+class State:
+    x: np.ndarray      # (dim, n) float64
+    u: np.ndarray      # (dim, n) float64
+    m: np.ndarray      # (n,) float64
+    ptype: np.ndarray  # (n,) uint8
+    pid: np.ndarray    # (n,) int32
+
+    @property
+    def n(self) -> int:
+        return int(self.m.shape[0])
+
+    def copy(self) -> "State":
+        return State(self.x.copy(), self.u.copy(), self.m.copy(), self.ptype.copy(),
+                     self.pid.copy())
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    params: Params
+    state: State
+    steps: int
+    precision: str         # "fp64" or "fp32" (pair math in FP32, FP64 integration)
+    description: str
+
+
+def stable_dt(h: float, c0: float, umax: float, nu: float, gmag: float) -> float:
+    """Fixed time step: min(0.25 h/(c0+U), 0.125 h^2/nu, 0.25 sqrt(h/|g|))."""
+    dt = 0.25 * h / (c0 + umax)
+    if nu > 0:
+        dt = min(dt, 0.125 * h * h / nu)
+    if gmag > 0:
+        dt = min(dt, 0.25 * math.sqrt(h / gmag))
+    return dt
+
+
+def lattice(counts, dx, origin) -> np.ndarray:
+    """Cell-centred lattice: origin + (i + 1/2) dx per axis, x fastest.  (dim, n)."""
+    axes = [origin[k] + (np.arange(counts[k], dtype=np.float64) + 0.5) * dx
+            for k in range(len(counts))]
+    grids = np.meshgrid(*axes, indexing="ij")
+    # x fastest in the flattened order
+    return np.stack([g.transpose().reshape(-1) for g in grids])
+
+
+def taylor_green(n_side: int, jitter: float = 0.0, seed: int = 0, hdx: float = 1.3,
+                 U: float = 1.0, Re: float = 100.0, kernel: int = CUBIC,
+                 cell_div: int = 1) -> Tuple[Params, State]:
+    """2D Taylor-Green vortex in the periodic unit box at t = 0.
+
+    u = -U cos(2 pi x) sin(2 pi y), v = U sin(2 pi x) cos(2 pi y) evaluated at
+    the (jittered) particle positions; nu = U L / Re; rho0 = 1; c0 = 10 U;
+    m = rho0 dx^2.
+    """
+    L = 1.0
+    dx = L / n_side
+    x = lattice((n_side, n_side), dx, (0.0, 0.0))
+    if jitter > 0:
+        rng = np.random.default_rng(seed)
+        x = x + rng.uniform(-jitter * dx, jitter * dx, size=x.shape)
+        x = np.mod(x, L)
+    u = np.empty_like(x)
+    u[0] = -U * np.cos(2 * np.pi * x[0]) * np.sin(2 * np.pi * x[1])
+    u[1] = U * np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1])
+    n = x.shape[1]
+    rho0 = 1.0
+    c0 = 10.0 * U
+    nu = U * L / Re
+    h = hdx * dx
+    params = Params(dim=2, kernel=kernel, h=h, rho0=rho0, c0=c0, nu=nu, eta=0.01,
+                    dt=stable_dt(h, c0, U, nu, 0.0), g=(0.0, 0.0, 0.0),
+                    lo=(0.0, 0.0, 0.0), hi=(L, L, 0.0), periodic=(1, 1, 0),
+                    cell_div=cell_div)
+    state = State(x=x, u=u, m=np.full(n, rho0 * dx * dx), ptype=np.zeros(n, np.uint8),
+                  pid=np.arange(n, dtype=np.int32))
+    return params, state
+
+
+def dam_break_3d(dx: float = 0.4 / 93, hdx: float = 1.3, layers: int = 3,
+                 tank=(1.6, 0.67, 0.6), column=(0.4, 0.4, 0.8),
+                 cell_div: int = 1) -> Tuple[Params, State]:
+    """3D dam-break-like box: fluid column in the tank corner, at rest; wall
+    particles fill `layers` lattice layers outside the tank floor and four
+    sides (open top).  z is up, g = (0, 0, -9.81), Wendland C2, rho0 = 1000,
+    c0 = 10 sqrt(2 g H) with H the column height, nu = alpha h c0 / (2(d+2))
+    with alpha = 0.1.
+    """
+    gz = 9.81
+    nfx, nfy, nfz = (int(round(c / dx)) for c in column)
+    fluid = lattice((nfx, nfy, nfz), dx, (0.0, 0.0, 0.0))
+    t = layers * dx
+    outer_lo = (-t, -t, -t)
+    cnt = (int(math.floor((tank[0] + 2 * t) / dx + 1e-9)),
+           int(math.floor((tank[1] + 2 * t) / dx + 1e-9)),
+           int(math.floor((tank[2] + t) / dx + 1e-9)))
+    box = lattice(cnt, dx, outer_lo)
+    inside = ((box[0] >= 0) & (box[0] < tank[0]) & (box[1] >= 0) & (box[1] < tank[1])
+              & (box[2] >= 0))
+    wall = box[:, ~inside]
+    x = np.concatenate([fluid, wall], axis=1)
+    nf, nw = fluid.shape[1], wall.shape[1]
+    n = nf + nw
+    rho0 = 1000.0
+    H = column[2]
+    c0 = 10.0 * math.sqrt(2 * gz * H)
+    h = hdx * dx
+    nu = 0.1 * h * c0 / (2 * (3 + 2))
+    R = 2 * h
+    lo = (-t - R, -t - R, -t - R)
+    hi = (tank[0] + t + R, tank[1] + t + R, max(tank[2], column[2]) + 2 * R)
+    params = Params(dim=3, kernel=WENDLAND, h=h, rho0=rho0, c0=c0, nu=nu, eta=0.01,
+                    dt=stable_dt(h, c0, 0.0, nu, gz), g=(0.0, 0.0, -gz),
+                    lo=lo, hi=hi, periodic=(0, 0, 0), cell_div=cell_div)
+    ptype = np.concatenate([np.zeros(nf, np.uint8), np.ones(nw, np.uint8)])
+    state = State(x=x, u=np.zeros_like(x), m=np.full(n, rho0 * dx ** 3), ptype=ptype,
+                  pid=np.arange(n, dtype=np.int32))
+    return params, state
+
+
+def periodic_cube(n_side: int = 256, jitter: float = 0.2, sigma_u: float = 0.1,
+                  hdx: float = 1.5, seed: int = 4, cell_div: int = 1) -> Tuple[Params, State]:
+    """3D periodic unit cube: jittered lattice, velocities N(0, sigma_u^2) per
+    component, Wendland C2, rho0 = 1, c0 = 10 max|u|, nu = alpha h c0/(2(d+2))
+    with alpha = 0.1."""
+    L = 1.0
+    dx = L / n_side
+    rng = np.random.default_rng(seed)
+    x = lattice((n_side,) * 3, dx, (0.0, 0.0, 0.0))
+    x = x + rng.uniform(-jitter * dx, jitter * dx, size=x.shape)
+    x = np.mod(x, L)
+    u = rng.normal(0.0, sigma_u, size=x.shape)
+    n = x.shape[1]
+    umax = float(np.sqrt((u * u).sum(axis=0)).max())
+    rho0 = 1.0
+    c0 = 10.0 * umax
+    h = hdx * dx
+    nu = 0.1 * h * c0 / (2 * (3 + 2))
+    params = Params(dim=3, kernel=WENDLAND, h=h, rho0=rho0, c0=c0, nu=nu, eta=0.01,
+                    dt=stable_dt(h, c0, umax, nu, 0.0), g=(0.0, 0.0, 0.0),
+                    lo=(0.0, 0.0, 0.0), hi=(L, L, L), periodic=(1, 1, 1), cell_div=cell_div)
+    state = State(x=x, u=u, m=np.full(n, rho0 * dx ** 3), ptype=np.zeros(n, np.uint8),
+                  pid=np.arange(n, dtype=np.int32))
+    return params, state
+
+
+def workload(name: str, **kw) -> Workload:
+    """The named benchmark/parity workloads.  Seeds are fixed per workload."""
+    if name == "tg64":
+        p, s = taylor_green(64, **kw)
+        return Workload(name, p, s, 50, "fp64",
+                        "2D Taylor-Green 64x64 lattice, Re=100, cubic h=1.3dx, 50 steps, FP64")
+    if name == "tg512":
+        p, s = taylor_green(512, jitter=0.1, seed=1, **kw)
+        return Workload(name, p, s, 1000, "fp32",
+                        "2D Taylor-Green 512x512 lattice jittered +-0.1dx, Re=100, cubic "
+                        "h=1.3dx, 1000 steps")
+    if name == "tg256":
+        p, s = taylor_green(256, **kw)
+        return Workload(name, p, s, 200, "fp32",
+                        "2D Taylor-Green 256x256, 200 steps, checkpoint every 20")
+    if name == "tg32":
+        p, s = taylor_green(32, **kw)
+        return Workload(name, p, s, 200, "fp64", "2D Taylor-Green 32x32 (adjoint companion)")
+    if name == "dambreak3d":
+        p, s = dam_break_3d(**kw)
+        return Workload(name, p, s, 500, "fp32",
+                        "3D dam-break box, Wendland C2 h=1.3dx, gravity, 500 steps")
+    if name == "cube256":
+        p, s = periodic_cube(**kw)
+        return Workload(name, p, s, 1, "fp32",
+                        "3D periodic cube 256^3 jittered +-0.2dx, Wendland C2 h=1.5dx, 1 step")
+    raise KeyError(name)
+
+
+def random_subset(n: int, k: int, seed: int = 123) -> np.ndarray:
+    """k distinct particle indices, sorted, for sampled checks of large runs."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=min(k, n), replace=False)).astype(np.int64)
