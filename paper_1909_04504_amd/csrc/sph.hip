@@ -1,0 +1,625 @@
+// Host side of the C ABI declared in include/sph.h: argument validation,
+// workspace layout and the launch sequences of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sph.h"
+#include "sph_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define SPH_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(SPH_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define SPH_TRY(expr)                \
+    do {                             \
+        int rc_ = (expr);            \
+        if (rc_ != SPH_OK) return rc_; \
+    } while (0)
+
+inline int launch_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SPH_EDEVICE, "launch of %s: %s", what, hipGetErrorString(e));
+    return SPH_OK;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + sph::kBlock - 1) / sph::kBlock); }
+
+// ---------------------------------------------------------------------------
+// Validation
+
+int check_params(const sph_params* p, bool need_dt) {
+    if (!p) return fail(SPH_EINVAL, "params is NULL");
+    if (p->dim != 2 && p->dim != 3) return fail(SPH_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->kernel != SPH_CUBIC_SPLINE && p->kernel != SPH_WENDLAND_C2)
+        return fail(SPH_EINVAL, "unknown kernel %d", p->kernel);
+    if (p->precision != SPH_FP64 && p->precision != SPH_FP32_MIXED)
+        return fail(SPH_EINVAL, "unknown precision %d", p->precision);
+    if (p->cell_div != 1 && p->cell_div != 2) return fail(SPH_EINVAL, "cell_div must be 1 or 2");
+    if (p->reserved != 0) return fail(SPH_EINVAL, "reserved field must be 0");
+    if (!(p->h > 0) || !std::isfinite(p->h)) return fail(SPH_EINVAL, "h must be > 0");
+    if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(SPH_EINVAL, "rho0 must be > 0");
+    if (!(p->c0 > 0) || !std::isfinite(p->c0)) return fail(SPH_EINVAL, "c0 must be > 0");
+    if (!(p->nu >= 0) || !std::isfinite(p->nu)) return fail(SPH_EINVAL, "nu must be >= 0");
+    if (!(p->eta >= 0) || !std::isfinite(p->eta)) return fail(SPH_EINVAL, "eta must be >= 0");
+    if (need_dt && (!(p->dt > 0) || !std::isfinite(p->dt))) return fail(SPH_EINVAL, "dt must be > 0");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->g[k])) return fail(SPH_EINVAL, "g must be finite");
+    for (int k = 0; k < p->dim; ++k) {
+        if (p->periodic[k] != 0 && p->periodic[k] != 1)
+            return fail(SPH_EINVAL, "periodic[%d] must be 0 or 1", k);
+        if (!std::isfinite(p->lo[k]) || !std::isfinite(p->hi[k]) || !(p->hi[k] > p->lo[k]))
+            return fail(SPH_EINVAL, "axis %d: need lo < hi (finite)", k);
+    }
+    return SPH_OK;
+}
+
+int make_grid(const sph_params* p, sph::Grid* G, int64_t* ncells) {
+    const double R = 2.0 * p->h;
+    *ncells = 1;
+    std::memset(G, 0, sizeof *G);
+    G->dim = p->dim;
+    G->S = p->cell_div;
+    for (int k = 0; k < 3; ++k) {
+        G->nc[k] = 1;
+        G->cs[k] = 1.0;
+        G->L[k] = 1.0;
+        G->lo[k] = 0.0;
+    }
+    for (int k = 0; k < p->dim; ++k) {
+        const double L = p->hi[k] - p->lo[k];
+        double f = std::floor(L * p->cell_div / R);
+        if (f < 1) f = 1;
+        if (f > 2147483647.0) return fail(SPH_EINVAL, "axis %d: too many cells", k);
+        const int64_t nc = (int64_t)f;
+        if (p->periodic[k] && nc < 2 * p->cell_div + 1)
+            return fail(SPH_EINVAL,
+                        "periodic axis %d has %lld cells; the %d-cell stencil needs at least %d",
+                        k, (long long)nc, 2 * p->cell_div + 1, 2 * p->cell_div + 1);
+        *ncells *= nc;
+        if (*ncells > ((int64_t)1 << 31)) return fail(SPH_EINVAL, "grid exceeds 2^31 cells");
+        G->nc[k] = (int)nc;
+        G->cs[k] = L / (double)nc;
+        G->L[k] = L;
+        G->lo[k] = p->lo[k];
+        G->periodic[k] = p->periodic[k];
+    }
+    return SPH_OK;
+}
+
+int check_particles(const sph_params* p, const sph_particles* pa) {
+    if (!pa) return fail(SPH_EINVAL, "particles is NULL");
+    if (pa->n < 1 || pa->n >= ((int64_t)1 << 31) - sph::kScanChunk)
+        return fail(SPH_EINVAL, "n must be in [1, 2^31 - %d)", sph::kScanChunk);
+    for (int k = 0; k < p->dim; ++k) {
+        if (!pa->x[k] || !pa->u[k] || !pa->a[k])
+            return fail(SPH_EINVAL, "x/u/a component %d is NULL", k);
+    }
+    if (!pa->rho || !pa->p || !pa->m || !pa->type || !pa->id)
+        return fail(SPH_EINVAL, "rho, p, m, type or id is NULL");
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (all offsets 256-byte aligned)
+
+struct Layout {
+    size_t flags, counts, start, chunks, key, tmp, perm, skey, ncnt;
+    size_t sx, su, sa, sm, stype, sid, srho, sp;
+    size_t pos, vel, rp, diag;
+    size_t bytes;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout make_layout(const sph_params* p, int64_t n, int64_t ncells) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t T = p->precision == SPH_FP64 ? 8 : 4;
+    const size_t d = (size_t)p->dim, N = (size_t)n;
+    const int64_t longest = (ncells + 1 > n + 1) ? ncells + 1 : n + 1;
+    const size_t nchunks = (size_t)((longest + sph::kScanChunk - 1) / sph::kScanChunk);
+    L.flags = take(256);
+    L.counts = take(4 * (size_t)ncells);
+    L.start = take(4 * ((size_t)ncells + 1));
+    L.chunks = take(8 * nchunks);
+    L.key = take(4 * N);
+    L.tmp = take(4 * N);
+    L.perm = take(4 * N);
+    L.skey = take(4 * N);
+    L.ncnt = take(4 * N);
+    L.sx = take(8 * d * N);
+    L.su = take(8 * d * N);
+    L.sa = take(T * d * N);
+    L.sm = take(8 * N);
+    L.stype = take(N);
+    L.sid = take(4 * N);
+    L.srho = take(T * N);
+    L.sp = take(T * N);
+    L.pos = take(4 * T * N);
+    L.vel = take(4 * T * N);
+    L.rp = take(2 * T * N);
+    L.diag = take(8 * 4 * (size_t)blocks_for(n));
+    L.bytes = off;
+    return L;
+}
+
+sph::State user_state(const sph_particles* pa) {
+    sph::State s;
+    for (int k = 0; k < 3; ++k) {
+        s.x[k] = pa->x[k];
+        s.u[k] = pa->u[k];
+        s.a[k] = pa->a[k];
+    }
+    s.rho = pa->rho;
+    s.p = pa->p;
+    s.m = pa->m;
+    s.type = pa->type;
+    s.id = pa->id;
+    return s;
+}
+
+sph::State ws_state(char* ws, const Layout& L, const sph_params* p, int64_t n) {
+    const size_t T = p->precision == SPH_FP64 ? 8 : 4;
+    sph::State s;
+    for (int k = 0; k < 3; ++k) {
+        const bool used = k < p->dim;
+        s.x[k] = used ? (double*)(ws + L.sx) + k * n : nullptr;
+        s.u[k] = used ? (double*)(ws + L.su) + k * n : nullptr;
+        s.a[k] = used ? (void*)(ws + L.sa + T * k * n) : nullptr;
+    }
+    s.rho = ws + L.srho;
+    s.p = ws + L.sp;
+    s.m = (double*)(ws + L.sm);
+    s.type = (uint8_t*)(ws + L.stype);
+    s.id = (int32_t*)(ws + L.sid);
+    return s;
+}
+
+template <typename T>
+sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
+    const double pi = 3.14159265358979323846;
+    const double h = p->h;
+    double sigma;
+    if (p->kernel == SPH_CUBIC_SPLINE)
+        sigma = p->dim == 2 ? 10.0 / (7.0 * pi * h * h) : 1.0 / (pi * h * h * h);
+    else
+        sigma = p->dim == 2 ? 7.0 / (4.0 * pi * h * h) : 21.0 / (16.0 * pi * h * h * h);
+    sph::PairConst<T> C;
+    C.R2 = (T)(4.0 * h * h);
+    C.inv_h = (T)(1.0 / h);
+    C.sigma = (T)sigma;
+    C.sigma_h2 = (T)(sigma / (h * h));
+    C.eta_h2 = (T)(p->eta * h * h);
+    C.four_nu = (T)(4.0 * p->nu);
+    for (int k = 0; k < 3; ++k) {
+        C.g[k] = (T)p->g[k];
+        C.cs[k] = (T)G.cs[k];
+    }
+    C.rho0 = (T)p->rho0;
+    C.inv_rho0 = (T)(1.0 / p->rho0);
+    C.B = (T)(p->rho0 * p->c0 * p->c0 / 7.0);
+    return C;
+}
+
+// ---------------------------------------------------------------------------
+// Launch sequences for one (dimension, kernel, pair precision)
+
+template <int DIM, int KERNEL, typename T>
+struct Engine {
+    using V4 = typename sph::Vec4<T>::type;
+    using V2 = typename sph::Vec2<T>::type;
+    const sph_params* prm;
+    sph::Grid G;
+    int64_t ncells;
+    int n;
+    char* ws;
+    Layout L;
+    hipStream_t st;
+    sph::PairConst<T> C;
+
+    uint32_t* flags() const { return (uint32_t*)(ws + L.flags); }
+    uint32_t* counts() const { return (uint32_t*)(ws + L.counts); }
+    uint32_t* start() const { return (uint32_t*)(ws + L.start); }
+    uint64_t* chunks() const { return (uint64_t*)(ws + L.chunks); }
+    uint32_t* key() const { return (uint32_t*)(ws + L.key); }
+    uint32_t* tmp() const { return (uint32_t*)(ws + L.tmp); }
+    uint32_t* perm() const { return (uint32_t*)(ws + L.perm); }
+    uint32_t* skey() const { return (uint32_t*)(ws + L.skey); }
+    uint32_t* ncnt() const { return (uint32_t*)(ws + L.ncnt); }
+    V4* pos() const { return (V4*)(ws + L.pos); }
+    V4* vel() const { return (V4*)(ws + L.vel); }
+    V2* rp() const { return (V2*)(ws + L.rp); }
+
+    int zero_counts() {
+        sph::k_fill_u32<<<blocks_for(ncells), sph::kBlock, 0, st>>>(ncells, 0u, counts());
+        return launch_check("k_fill_u32");
+    }
+
+    // exclusive scan of `len` u32 counts into out[0..len]
+    template <typename OUT>
+    int scan(const uint32_t* in, int64_t len, OUT* out) {
+        const unsigned nch = (unsigned)((len + sph::kScanChunk - 1) / sph::kScanChunk);
+        sph::k_chunk_sum<<<nch, sph::kBlock, 0, st>>>(in, len, chunks());
+        SPH_TRY(launch_check("k_chunk_sum"));
+        sph::k_chunk_scan<OUT><<<nch, sph::kBlock, 0, st>>>(in, len, chunks(), out);
+        return launch_check("k_chunk_scan");
+    }
+
+    // hash (with the opening half kick + drift if drift), counting sort, and
+    // gather of src into dst in sorted order with pair records packed.
+    int sort_into(const sph::State& src, const sph::State& dst, bool drift, bool copy_derived) {
+        const unsigned nb = blocks_for(n);
+        using TA = T;
+        sph::k_drift_hash<DIM, TA><<<nb, sph::kBlock, 0, st>>>(n, src, G, 0.5 * prm->dt, prm->dt,
+                                                              drift ? 1 : 0, key(), counts(), flags());
+        SPH_TRY(launch_check("k_drift_hash"));
+        SPH_TRY(scan<uint32_t>(counts(), ncells, start()));
+        sph::k_scatter<<<nb, sph::kBlock, 0, st>>>(n, key(), start(), counts(), tmp());
+        SPH_TRY(launch_check("k_scatter"));
+        sph::k_rank_gather<DIM, T><<<nb, sph::kBlock, 0, st>>>(n, tmp(), key(), start(), src, dst, G,
+                                                             perm(), skey(), pos(), vel(),
+                                                             copy_derived ? 1 : 0);
+        return launch_check("k_rank_gather");
+    }
+
+    int density(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_eos) {
+        sph::k_density<DIM, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+            n, G, C, skey(), pos(), cs, ce, (T*)s.rho, (T*)s.p, rp(), with_eos ? 1 : 0);
+        return launch_check("k_density");
+    }
+
+    int momentum(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool kick) {
+        sph::k_momentum<DIM, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+            n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, s, kick ? 1 : 0, 0.5 * prm->dt);
+        return launch_check("k_momentum");
+    }
+
+    int pack(const sph::State& s, bool with_rp) {
+        sph::k_pack<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, s, G, skey(), pos(), vel(),
+                                                                  rp(), with_rp ? 1 : 0);
+        return launch_check("k_pack");
+    }
+
+    int copy(const sph::State& src, const sph::State& dst) {
+        sph::k_copy_state<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, src, dst);
+        return launch_check("k_copy_state");
+    }
+
+    int diag(const sph::State& s, double* out) {
+        const unsigned nb = blocks_for(n);
+        double* part = (double*)(ws + L.diag);
+        sph::k_diag_partial<DIM><<<nb, sph::kBlock, 0, st>>>(n, s, part);
+        SPH_TRY(launch_check("k_diag_partial"));
+        sph::k_diag_final<DIM><<<1, sph::kBlock, 0, st>>>((int)nb, part, out);
+        return launch_check("k_diag_final");
+    }
+
+    // --- entry points ---------------------------------------------------
+
+    int bin_sort(sph_particles* pa, uint32_t* cs_out, uint32_t* ce_out) {
+        const sph::State user = user_state(pa);
+        const sph::State tmp_state = ws_state(ws, L, prm, n);
+        SPH_TRY(zero_counts());
+        SPH_TRY(sort_into(user, tmp_state, false, true));
+        SPH_TRY(copy(tmp_state, user));
+        sph::k_cell_ranges<<<blocks_for(ncells), sph::kBlock, 0, st>>>(ncells, start(), cs_out, ce_out);
+        return launch_check("k_cell_ranges");
+    }
+
+    int density_only(sph_particles* pa, const uint32_t* cs, const uint32_t* ce) {
+        const sph::State user = user_state(pa);
+        SPH_TRY(pack(user, false));
+        return density(user, cs, ce, false);
+    }
+
+    int momentum_only(sph_particles* pa, const uint32_t* cs, const uint32_t* ce) {
+        const sph::State user = user_state(pa);
+        SPH_TRY(pack(user, true));
+        return momentum(user, cs, ce, false);
+    }
+
+    int eos_only(sph_particles* pa) {
+        sph::k_eos<T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, C, (const T*)pa->rho, (T*)pa->p);
+        return launch_check("k_eos");
+    }
+
+    int neighbors(const sph_particles* pa, const uint32_t* cs, const uint32_t* ce, int64_t capacity,
+                  int64_t* offsets, int32_t* nbr, int64_t* total) {
+        const sph::State user = user_state(pa);
+        SPH_TRY(pack(user, false));
+        sph::k_nbr_count<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, G, C, skey(), pos(), cs,
+                                                                       ce, ncnt());
+        SPH_TRY(launch_check("k_nbr_count"));
+        SPH_TRY(scan<int64_t>(ncnt(), n, offsets));
+        int64_t tot = 0;
+        SPH_HIP(hipMemcpyAsync(&tot, offsets + n, sizeof tot, hipMemcpyDeviceToHost, st));
+        SPH_HIP(hipStreamSynchronize(st));
+        *total = tot;
+        if (tot > capacity)
+            return fail(SPH_ECAPACITY, "neighbour list needs %lld entries, capacity %lld",
+                        (long long)tot, (long long)capacity);
+        if (tot > 0 && !nbr) return fail(SPH_EINVAL, "nbr is NULL");
+        sph::k_nbr_fill<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, G, C, skey(), pos(), cs,
+                                                                      ce, offsets, nbr);
+        return launch_check("k_nbr_fill");
+    }
+
+    int step(sph_particles* pa, int64_t nsteps, int prime, double* diag_out) {
+        const sph::State user = user_state(pa);
+        const sph::State wst = ws_state(ws, L, prm, n);
+        sph::State cur = user, nxt = wst;
+        const uint32_t* cs = start();
+        const uint32_t* ce = start() + 1;
+        SPH_TRY(zero_counts());
+        if (prime) {
+            SPH_TRY(sort_into(cur, nxt, false, false));
+            SPH_TRY(density(nxt, cs, ce, true));
+            SPH_TRY(momentum(nxt, cs, ce, false));
+            std::swap(cur, nxt);
+        }
+        for (int64_t s = 0; s < nsteps; ++s) {
+            SPH_TRY(sort_into(cur, nxt, true, false));
+            SPH_TRY(density(nxt, cs, ce, true));
+            SPH_TRY(momentum(nxt, cs, ce, true));
+            if (diag_out) SPH_TRY(diag(nxt, diag_out + s * (1 + DIM)));
+            std::swap(cur, nxt);
+        }
+        if (cur.m != user.m) SPH_TRY(copy(cur, user));
+        return SPH_OK;
+    }
+};
+
+template <template <int, int, typename> class F, typename... Args>
+int dispatch(const sph_params* p, Args&&... args) {
+    const bool f64 = p->precision == SPH_FP64;
+    if (p->dim == 2) {
+        if (p->kernel == SPH_CUBIC_SPLINE)
+            return f64 ? F<2, 0, double>::run(p, args...) : F<2, 0, float>::run(p, args...);
+        return f64 ? F<2, 1, double>::run(p, args...) : F<2, 1, float>::run(p, args...);
+    }
+    if (p->kernel == SPH_CUBIC_SPLINE)
+        return f64 ? F<3, 0, double>::run(p, args...) : F<3, 0, float>::run(p, args...);
+    return f64 ? F<3, 1, double>::run(p, args...) : F<3, 1, float>::run(p, args...);
+}
+
+// Common preparation: grid, layout, workspace check, engine.
+template <int DIM, int KERNEL, typename T>
+int make_engine(const sph_params* p, const sph_particles* pa, void* ws, size_t ws_bytes,
+                void* stream, Engine<DIM, KERNEL, T>* E) {
+    int64_t ncells;
+    SPH_TRY(make_grid(p, &E->G, &ncells));
+    E->prm = p;
+    E->ncells = ncells;
+    E->n = (int)pa->n;
+    E->L = make_layout(p, pa->n, ncells);
+    if (!ws) return fail(SPH_EINVAL, "workspace is NULL");
+    if ((uintptr_t)ws % 256 != 0) return fail(SPH_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < E->L.bytes)
+        return fail(SPH_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, E->L.bytes);
+    E->ws = (char*)ws;
+    E->st = (hipStream_t)stream;
+    E->C = pair_const<T>(p, E->G);
+    return SPH_OK;
+}
+
+template <int DIM, int KERNEL, typename T>
+struct RunBinSort {
+    static int run(const sph_params* p, sph_particles* pa, void* ws, size_t wb, uint32_t* cs,
+                   uint32_t* ce, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        SPH_TRY(make_engine(p, pa, ws, wb, st, &E));
+        return E.bin_sort(pa, cs, ce);
+    }
+};
+
+template <int DIM, int KERNEL, typename T>
+struct RunDensity {
+    static int run(const sph_params* p, sph_particles* pa, const uint32_t* cs, const uint32_t* ce,
+                   void* ws, size_t wb, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        SPH_TRY(make_engine(p, pa, ws, wb, st, &E));
+        return E.density_only(pa, cs, ce);
+    }
+};
+
+template <int DIM, int KERNEL, typename T>
+struct RunMomentum {
+    static int run(const sph_params* p, sph_particles* pa, const uint32_t* cs, const uint32_t* ce,
+                   void* ws, size_t wb, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        SPH_TRY(make_engine(p, pa, ws, wb, st, &E));
+        return E.momentum_only(pa, cs, ce);
+    }
+};
+
+template <int DIM, int KERNEL, typename T>
+struct RunEos {
+    static int run(const sph_params* p, sph_particles* pa, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        E.prm = p;
+        E.n = (int)pa->n;
+        E.st = (hipStream_t)st;
+        int64_t ncells;
+        SPH_TRY(make_grid(p, &E.G, &ncells));
+        E.C = pair_const<T>(p, E.G);
+        return E.eos_only(pa);
+    }
+};
+
+template <int DIM, int KERNEL, typename T>
+struct RunNeighbors {
+    static int run(const sph_params* p, const sph_particles* pa, const uint32_t* cs,
+                   const uint32_t* ce, int64_t cap, int64_t* off, int32_t* nbr, int64_t* total,
+                   void* ws, size_t wb, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        SPH_TRY(make_engine(p, pa, ws, wb, st, &E));
+        return E.neighbors(pa, cs, ce, cap, off, nbr, total);
+    }
+};
+
+template <int DIM, int KERNEL, typename T>
+struct RunStep {
+    static int run(const sph_params* p, sph_particles* pa, int64_t nsteps, int prime, void* ws,
+                   size_t wb, double* diag, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        SPH_TRY(make_engine(p, pa, ws, wb, st, &E));
+        return E.step(pa, nsteps, prime, diag);
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* sph_last_error(void) { return g_err.c_str(); }
+
+int sph_grid(const sph_params* prm, int64_t nc[3], int64_t* ncells) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, false));
+    if (!nc || !ncells) return fail(SPH_EINVAL, "output pointer is NULL");
+    sph::Grid G;
+    SPH_TRY(make_grid(prm, &G, ncells));
+    for (int k = 0; k < 3; ++k) nc[k] = G.nc[k];
+    return SPH_OK;
+}
+
+size_t sph_workspace_bytes(const sph_params* prm, int64_t n, int64_t adjoint_k) {
+    g_err.clear();
+    if (check_params(prm, false) != SPH_OK) return 0;
+    if (n < 1 || n >= ((int64_t)1 << 31) - sph::kScanChunk) {
+        fail(SPH_EINVAL, "n out of range");
+        return 0;
+    }
+    if (adjoint_k < 0) {
+        fail(SPH_EINVAL, "adjoint_k must be >= 0");
+        return 0;
+    }
+    sph::Grid G;
+    int64_t ncells;
+    if (make_grid(prm, &G, &ncells) != SPH_OK) return 0;
+    return make_layout(prm, n, ncells).bytes;
+}
+
+int sph_bin_sort(const sph_params* prm, sph_particles* pa, void* ws, size_t ws_bytes,
+                 uint32_t* cell_start, uint32_t* cell_end, void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, false));
+    SPH_TRY(check_particles(prm, pa));
+    if (!cell_start || !cell_end) return fail(SPH_EINVAL, "cell_start/cell_end is NULL");
+    return dispatch<RunBinSort>(prm, pa, ws, ws_bytes, cell_start, cell_end, stream);
+}
+
+int sph_neighbors(const sph_params* prm, const sph_particles* pa, const uint32_t* cell_start,
+                  const uint32_t* cell_end, int64_t capacity, int64_t* offsets, int32_t* nbr,
+                  int64_t* total, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, false));
+    SPH_TRY(check_particles(prm, pa));
+    if (!cell_start || !cell_end || !offsets || !total)
+        return fail(SPH_EINVAL, "cell ranges, offsets or total is NULL");
+    if (capacity < 0) return fail(SPH_EINVAL, "capacity must be >= 0");
+    return dispatch<RunNeighbors>(prm, pa, cell_start, cell_end, capacity, offsets, nbr, total, ws,
+                                  ws_bytes, stream);
+}
+
+int sph_density(const sph_params* prm, sph_particles* pa, const uint32_t* cell_start,
+                const uint32_t* cell_end, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, false));
+    SPH_TRY(check_particles(prm, pa));
+    if (!cell_start || !cell_end) return fail(SPH_EINVAL, "cell_start/cell_end is NULL");
+    return dispatch<RunDensity>(prm, pa, cell_start, cell_end, ws, ws_bytes, stream);
+}
+
+int sph_eos(const sph_params* prm, sph_particles* pa, void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, false));
+    if (!pa || pa->n < 1 || pa->n >= ((int64_t)1 << 31) || !pa->rho || !pa->p)
+        return fail(SPH_EINVAL, "need n >= 1 and rho, p");
+    return dispatch<RunEos>(prm, pa, stream);
+}
+
+int sph_momentum(const sph_params* prm, sph_particles* pa, const uint32_t* cell_start,
+                 const uint32_t* cell_end, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, false));
+    SPH_TRY(check_particles(prm, pa));
+    if (!cell_start || !cell_end) return fail(SPH_EINVAL, "cell_start/cell_end is NULL");
+    return dispatch<RunMomentum>(prm, pa, cell_start, cell_end, ws, ws_bytes, stream);
+}
+
+int sph_step(const sph_params* prm, sph_particles* pa, int64_t nsteps, int prime_accel, void* ws,
+             size_t ws_bytes, double* diag, void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, true));
+    SPH_TRY(check_particles(prm, pa));
+    if (nsteps < 0) return fail(SPH_EINVAL, "nsteps must be >= 0");
+    if (prime_accel != 0 && prime_accel != 1) return fail(SPH_EINVAL, "prime_accel must be 0 or 1");
+    return dispatch<RunStep>(prm, pa, nsteps, prime_accel, ws, ws_bytes, diag, stream);
+}
+
+int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t k,
+                      const double* lam_in, double* lam_out, double* dJ_dnu, void* ws,
+                      size_t ws_bytes, void* stream) {
+    g_err.clear();
+    (void)prm; (void)ckpt; (void)k; (void)lam_in; (void)lam_out; (void)dJ_dnu; (void)ws;
+    (void)ws_bytes; (void)stream;
+    return fail(SPH_EINVAL, "sph_step_backward: not available in this build");
+}
+
+int sph_accel_backward(const sph_params* prm, const sph_particles* st, const double* lam_a,
+                       double* lam_x, double* lam_u, double* dJ_dnu, void* ws, size_t ws_bytes,
+                       void* stream) {
+    g_err.clear();
+    (void)prm; (void)st; (void)lam_a; (void)lam_x; (void)lam_u; (void)dJ_dnu; (void)ws;
+    (void)ws_bytes; (void)stream;
+    return fail(SPH_EINVAL, "sph_accel_backward: not available in this build");
+}
+
+int sph_check(void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!ws || ws_bytes < 256) return fail(SPH_EINVAL, "workspace is NULL or too small");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t flags = 0;
+    SPH_HIP(hipMemcpyAsync(&flags, ws, sizeof flags, hipMemcpyDeviceToHost, st));
+    SPH_HIP(hipStreamSynchronize(st));
+    if (flags) {
+        SPH_HIP(hipMemsetAsync(ws, 0, sizeof flags, st));
+        SPH_HIP(hipStreamSynchronize(st));
+    }
+    if (flags & sph::kFlagNonFinite) return fail(SPH_ENONFINITE, "non-finite position or velocity");
+    if (flags & sph::kFlagOutside)
+        return fail(SPH_EDOMAIN, "particle outside a non-periodic domain (clamped to edge cells)");
+    return SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,666 @@
+// Device kernels of the gfx950 WCSPH hot path.
+//
+// Method (arXiv:1909.04504, Section 2): summation density (eq. 2), Tait EOS
+// (eq. eos), momentum with pressure and viscous terms (eqs. mom:sph,
+// mom:sph:press, mom:sph:visc), predictor-corrector integration (Sec. 2.1),
+// uniform-cell neighbour search (Sec. 2.2).
+//
+// Design for CDNA4 (wave64, 256 CUs in 8 XCDs):
+//  * Particles are kept sorted by cell key, so the particles of a stencil row
+//    of cells are contiguous and every pair loop walks contiguous,
+//    cache-resident slot ranges.  The sort is a counting sort on cell keys:
+//    integer atomics count particles per cell, a two-kernel scan turns counts
+//    into cell offsets, an atomic scatter groups particles by cell and a
+//    per-cell rank (number of smaller previous indices in the same cell)
+//    makes the result identical to a stable sort, hence deterministic.
+//  * Pair records are packed per sorted slot: (delta, m) and (v) as 4-vectors
+//    and (rho, P = p/rho^2) as a 2-vector, where delta is the position
+//    relative to the origin of the particle's own cell.  Separations are
+//    r_ij = (delta_i - delta_j) - o cs, o the stencil offset of j's cell, so
+//    swapping i and j negates every rounded operation: r_ji = -r_ij bitwise
+//    and the neighbour predicate is exactly symmetric.  In mixed precision
+//    delta is float: a cell-relative float keeps ~1e-9 absolute accuracy
+//    where an absolute float position would keep ~1e-7.
+//  * No floating-point atomics anywhere: every sum is formed by one thread in
+//    a fixed order, so results are bitwise reproducible run to run.
+//  * Integration (kick, drift, wrap) is FP64 with contraction disabled, so
+//    it rounds exactly as the plain definition does.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sph {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
+constexpr int kScanItems = 16;       // items per thread in the scans
+constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dealt round-robin
+
+enum : uint32_t { kFlagOutside = 1u, kFlagNonFinite = 2u };
+
+// Cell grid (Sec. 2.2): cs_k >= R / S on every used axis, S = stencil reach.
+struct Grid {
+    int nc[3];
+    int S;
+    int periodic[3];
+    int dim;
+    double lo[3];
+    double L[3];
+    double cs[3];
+};
+
+// Particle state arrays (device pointers); a, rho, p are of the pair type T.
+struct State {
+    double* x[3];
+    double* u[3];
+    void* a[3];
+    void* rho;
+    void* p;
+    double* m;
+    uint8_t* type;
+    int32_t* id;
+};
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// Constants of the pair terms in the pair precision T.
+template <typename T>
+struct PairConst {
+    T R2;          // (2h)^2
+    T inv_h;       // 1/h
+    T sigma;       // kernel normalisation (includes h^-dim)
+    T sigma_h2;    // sigma / h^2: scale of F = (dW/dr)/r
+    T eta_h2;      // eta h^2
+    T four_nu;     // 4 nu
+    T g[3];        // body acceleration
+    T cs[3];       // cell sizes
+    T rho0, inv_rho0, B;  // Tait: p = B((rho/rho0)^7 - 1)
+};
+
+// ---------------------------------------------------------------------------
+// Precision-generic helpers.  Mixed precision uses the hardware square root
+// and reciprocal (1 ulp); FP64 uses the correctly rounded library forms.
+__device__ __forceinline__ float p_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double p_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float p_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double p_rcp(double x) { return 1.0 / x; }
+
+// Smoothing kernel W(q) = sigma w(q), q = r/h, support q < 2.
+//   cubic spline (M4):  1 - 1.5 q^2 + 0.75 q^3 (q < 1);  0.25 (2 - q)^3 (q < 2)
+//   Wendland C2:        (1 - q/2)^4 (2 q + 1)
+template <int KERNEL, typename T>
+__device__ __forceinline__ T kernel_w(T q, T sigma) {
+    if (KERNEL == 0) {
+        const T t = T(2) - q;
+        const T outer = T(0.25) * t * t * t;
+        const T inner = T(1) - q * q * (T(1.5) - T(0.75) * q);
+        return sigma * (q < T(1) ? inner : outer);
+    } else {
+        const T t = T(1) - T(0.5) * q;
+        const T t2 = t * t;
+        return sigma * (t2 * t2 * (T(2) * q + T(1)));
+    }
+}
+
+// F(q) = (dW/dr) / r, so that grad_i W_ij = F r_ij.
+//   cubic:    sigma/h^2 (-3 + 2.25 q)  (q < 1);  -0.75 sigma/h^2 (2-q)^2 / q  (q < 2)
+//   Wendland: -5 sigma/h^2 (1 - q/2)^3
+template <int KERNEL, typename T>
+__device__ __forceinline__ T kernel_f(T q, T sigma_h2) {
+    if (KERNEL == 0) {
+        const T t = T(2) - q;
+        if (q < T(1)) return sigma_h2 * (T(-3) + T(2.25) * q);
+        return T(-0.75) * sigma_h2 * t * t * p_rcp(q);
+    } else {
+        const T t = T(1) - T(0.5) * q;
+        return T(-5) * sigma_h2 * t * t * t;
+    }
+}
+
+// Tait EOS with the seventh power as r2 = r r, r4 = r2 r2, r7 = r4 r2 r.
+template <typename T>
+__device__ __forceinline__ T tait(T rho, const PairConst<T>& C) {
+    const T r = rho * C.inv_rho0;
+    const T r2 = r * r;
+    const T r4 = r2 * r2;
+    return C.B * (r4 * r2 * r - T(1));
+}
+
+// Map the hardware workgroup id to a logical block so that each XCD (blocks
+// are dealt to XCDs round-robin) works on one contiguous range of sorted
+// particles: neighbour data then stays in that XCD's L2.
+__device__ __forceinline__ int xcd_block() {
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int x = b % kNumXcd, k = b / kNumXcd;
+    const int per = nb / kNumXcd, rem = nb % kNumXcd;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ void decode_key(uint32_t key, const Grid& G, int c[3]) {
+    c[0] = (int)(key % (uint32_t)G.nc[0]);
+    const uint32_t t = key / (uint32_t)G.nc[0];
+    c[1] = (int)(t % (uint32_t)G.nc[1]);
+    c[2] = (int)(t / (uint32_t)G.nc[1]);
+}
+
+// cell coordinate clamp(floor((x - lo)/cs), 0, nc-1); NaN goes to 0.  A
+// clamp on a non-periodic axis marks the particle as outside the box (its
+// neighbours are still found: all of them are clamped into the same edge
+// cells or lie in the stencil).  On a periodic axis a clamp only absorbs the
+// rounding of a wrapped coordinate just below hi.
+__device__ __forceinline__ int cell_coord(double x, const Grid& G, int k, bool* outside) {
+    const double f = floor((x - G.lo[k]) / G.cs[k]);
+    if (!(f >= 0.0)) {
+        *outside |= !G.periodic[k];
+        return 0;
+    }
+    if (f > (double)(G.nc[k] - 1)) {
+        *outside |= !G.periodic[k];
+        return G.nc[k] - 1;
+    }
+    return (int)f;
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour loop: calls f(j, dx, dy, dz, r2) for every sorted slot j with
+// |r_ij|^2 < R^2 in the (2S+1)^dim stencil cells of i's cell (self included).
+template <int DIM, typename T, typename Fn>
+__device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst<T>& C,
+                                                  uint32_t key, T dix, T diy, T diz,
+                                                  const typename Vec4<T>::type* __restrict__ pos,
+                                                  const uint32_t* __restrict__ cstart,
+                                                  const uint32_t* __restrict__ cend, uint32_t n,
+                                                  Fn&& f) {
+    int c[3];
+    decode_key(key, G, c);
+    const int S = G.S;
+    const int zlo = DIM == 3 ? -S : 0, zhi = DIM == 3 ? S : 0;
+    for (int oz = zlo; oz <= zhi; ++oz) {
+        int cz = 0;
+        if (DIM == 3) {
+            cz = c[2] + oz;
+            if (G.periodic[2]) {
+                cz = cz < 0 ? cz + G.nc[2] : (cz >= G.nc[2] ? cz - G.nc[2] : cz);
+            } else if (cz < 0 || cz >= G.nc[2]) {
+                continue;
+            }
+        }
+        const T offz = T(oz) * C.cs[2];
+        for (int oy = -S; oy <= S; ++oy) {
+            int cy = c[1] + oy;
+            if (G.periodic[1]) {
+                cy = cy < 0 ? cy + G.nc[1] : (cy >= G.nc[1] ? cy - G.nc[1] : cy);
+            } else if (cy < 0 || cy >= G.nc[1]) {
+                continue;
+            }
+            const T offy = T(oy) * C.cs[1];
+            const uint32_t row = (uint32_t)G.nc[0] * ((uint32_t)cy + (uint32_t)G.nc[1] * (uint32_t)cz);
+            for (int ox = -S; ox <= S; ++ox) {
+                int cx = c[0] + ox;
+                if (G.periodic[0]) {
+                    cx = cx < 0 ? cx + G.nc[0] : (cx >= G.nc[0] ? cx - G.nc[0] : cx);
+                } else if (cx < 0 || cx >= G.nc[0]) {
+                    continue;
+                }
+                const T offx = T(ox) * C.cs[0];
+                const uint32_t cell = row + (uint32_t)cx;
+                const uint32_t b = cstart[cell];
+                uint32_t e = cend[cell];
+                e = e < n ? e : n;
+                for (uint32_t j = b; j < e; ++j) {
+                    const typename Vec4<T>::type rj = pos[j];
+                    const T dx = (dix - rj.x) - offx;
+                    const T dy = (diy - rj.y) - offy;
+                    T r2 = dx * dx + dy * dy;
+                    T dz = T(0);
+                    if (DIM == 3) {
+                        dz = (diz - rj.z) - offz;
+                        r2 += dz * dz;
+                    }
+                    if (r2 < C.R2) f(j, rj, dx, dy, dz, r2);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hash (and optionally the opening half kick + drift + periodic wrap):
+//   v = u + dt/2 a;  x <- wrap(x + dt v)   (fluid only; walls have v = 0)
+// then key = cell of x, counts[key] += 1.
+template <int DIM, typename TA>
+__global__ __launch_bounds__(kBlock) void k_drift_hash(int n, State S, Grid G, double hdt,
+                                                       double dt, int drift,
+                                                       uint32_t* __restrict__ key,
+                                                       uint32_t* __restrict__ counts,
+                                                       uint32_t* __restrict__ flags) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    bool outside = false, nonfinite = false;
+    int c[3] = {0, 0, 0};
+    const bool fluid = S.type[i] == 0;
+    for (int k = 0; k < DIM; ++k) {
+        double x = S.x[k][i];
+        if (drift) {
+            double v = 0.0;
+            if (fluid) {
+                const double a = (double)((const TA*)S.a[k])[i];
+                v = S.u[k][i] + hdt * a;
+                x = x + dt * v;
+                if (G.periodic[k]) {
+                    const double hi = G.lo[k] + G.L[k];
+                    double y = x - G.L[k] * floor((x - G.lo[k]) / G.L[k]);
+                    if (y >= hi) y = G.lo[k];
+                    x = y;
+                }
+                S.x[k][i] = x;
+            }
+            S.u[k][i] = v;
+            nonfinite |= !isfinite(v);
+        }
+        nonfinite |= !isfinite(x);
+        c[k] = cell_coord(x, G, k, &outside);
+    }
+    const uint32_t kk = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
+    key[i] = kk;
+    atomicAdd(&counts[kk], 1u);
+    if (outside) atomicOr(flags, kFlagOutside);
+    if (nonfinite) atomicOr(flags, kFlagNonFinite);
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of one value per thread (256 threads, wave64).
+template <typename V>
+__device__ __forceinline__ V block_exclusive_scan(V v, V* total) {
+    __shared__ V wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    V incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const V o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    V before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) {
+        before += k < w ? wsum[k] : V(0);
+        all += wsum[k];
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + incl - v;
+}
+
+// Sum of each chunk of kScanChunk input counts.
+__global__ __launch_bounds__(kBlock) void k_chunk_sum(const uint32_t* __restrict__ in, int64_t n,
+                                                      uint64_t* __restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) s += in[base + k];
+    uint64_t tot;
+    block_exclusive_scan<uint64_t>(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the input counts: out[i] = sum_{k<i} in[k], out[n] = total.
+template <typename OUT>
+__global__ __launch_bounds__(kBlock) void k_chunk_scan(const uint32_t* __restrict__ in, int64_t n,
+                                                       const uint64_t* __restrict__ sums,
+                                                       OUT* __restrict__ out) {
+    // offset of this chunk: sum of the chunk sums before it
+    uint64_t off = 0;
+    for (int c = threadIdx.x; c < (int)blockIdx.x; c += kBlock) off += sums[c];
+    uint64_t offtot;
+    block_exclusive_scan<uint64_t>(off, &offtot);
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint64_t chunk_total;
+    uint64_t run = offtot + block_exclusive_scan<uint64_t>(s, &chunk_total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = (OUT)run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (OUT)(offtot + chunk_total);
+}
+
+// Scatter particles into their cell's slot range; counts return to zero.
+__global__ __launch_bounds__(kBlock) void k_scatter(int n, const uint32_t* __restrict__ key,
+                                                    const uint32_t* __restrict__ start,
+                                                    uint32_t* __restrict__ counts,
+                                                    uint32_t* __restrict__ tmp) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = key[i];
+    const uint32_t old = atomicSub(&counts[k], 1u);
+    tmp[start[k] + old - 1u] = (uint32_t)i;
+}
+
+// Stable order inside each cell: slot s holds particle i = tmp[s]; its final
+// slot is start[key] + (number of particles of the same cell with a smaller
+// index).  Gathers the state into that slot and packs the pair records.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* __restrict__ tmp,
+                                                        const uint32_t* __restrict__ key,
+                                                        const uint32_t* __restrict__ start,
+                                                        State src, State dst, Grid G,
+                                                        uint32_t* __restrict__ perm,
+                                                        uint32_t* __restrict__ skey,
+                                                        typename Vec4<T>::type* __restrict__ pos,
+                                                        typename Vec4<T>::type* __restrict__ vel,
+                                                        int copy_derived) {
+#pragma clang fp contract(off)
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t i = tmp[s];
+    const uint32_t k = key[i];
+    const uint32_t b = start[k], e = start[k + 1];
+    uint32_t rank = 0;
+    for (uint32_t t = b; t < e; ++t) rank += tmp[t] < i ? 1u : 0u;
+    const uint32_t d = b + rank;
+    perm[d] = i;
+    skey[d] = k;
+    int c[3];
+    decode_key(k, G, c);
+    T del[3] = {T(0), T(0), T(0)};
+    T vv[3] = {T(0), T(0), T(0)};
+    for (int q = 0; q < DIM; ++q) {
+        const double x = src.x[q][i];
+        const double u = src.u[q][i];
+        dst.x[q][d] = x;
+        dst.u[q][d] = u;
+        if (copy_derived) ((T*)dst.a[q])[d] = ((const T*)src.a[q])[i];
+        del[q] = (T)(x - (G.lo[q] + (double)c[q] * G.cs[q]));
+        vv[q] = (T)u;
+    }
+    const double m = src.m[i];
+    dst.m[d] = m;
+    dst.type[d] = src.type[i];
+    dst.id[d] = src.id[i];
+    if (copy_derived) {
+        ((T*)dst.rho)[d] = ((const T*)src.rho)[i];
+        ((T*)dst.p)[d] = ((const T*)src.p)[i];
+    }
+    typename Vec4<T>::type pr, vr;
+    pr.x = del[0]; pr.y = del[1]; pr.z = del[2]; pr.w = (T)m;
+    vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
+    pos[d] = pr;
+    vel[d] = vr;
+}
+
+// Pack pair records of an already sorted state (standalone evaluations):
+// key = cell of x, (delta, m), (u), and (rho, p/rho^2) if with_rp.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
+                                                 uint32_t* __restrict__ skey,
+                                                 typename Vec4<T>::type* __restrict__ pos,
+                                                 typename Vec4<T>::type* __restrict__ vel,
+                                                 typename Vec2<T>::type* __restrict__ rp,
+                                                 int with_rp) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    bool outside = false;
+    int c[3] = {0, 0, 0};
+    T del[3] = {T(0), T(0), T(0)};
+    T vv[3] = {T(0), T(0), T(0)};
+    for (int q = 0; q < DIM; ++q) {
+        const double x = S.x[q][i];
+        c[q] = cell_coord(x, G, q, &outside);
+        del[q] = (T)(x - (G.lo[q] + (double)c[q] * G.cs[q]));
+        vv[q] = (T)S.u[q][i];
+    }
+    skey[i] = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
+    typename Vec4<T>::type pr, vr;
+    pr.x = del[0]; pr.y = del[1]; pr.z = del[2]; pr.w = (T)S.m[i];
+    vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
+    pos[i] = pr;
+    vel[i] = vr;
+    if (with_rp) {
+        const T rho = ((const T*)S.rho)[i];
+        const T p = ((const T*)S.p)[i];
+        typename Vec2<T>::type v2;
+        v2.x = rho;
+        v2.y = p / (rho * rho);
+        rp[i] = v2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Summation density (eq. 2) and, if with_eos, the Tait EOS (eq. eos) with
+// P = p / rho^2 packed for the momentum pass.
+template <int DIM, int KERNEL, typename T>
+__global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
+                                                    const uint32_t* __restrict__ skey,
+                                                    const typename Vec4<T>::type* __restrict__ pos,
+                                                    const uint32_t* __restrict__ cstart,
+                                                    const uint32_t* __restrict__ cend,
+                                                    T* __restrict__ rho_out, T* __restrict__ p_out,
+                                                    typename Vec2<T>::type* __restrict__ rp,
+                                                    int with_eos) {
+    const int i = xcd_block() * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const typename Vec4<T>::type ri = pos[i];
+    T acc = T(0);
+    for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
+                              [&](uint32_t j, const typename Vec4<T>::type& rj, T, T, T, T r2) {
+                                  const T q = p_sqrt(r2) * C.inv_h;
+                                  acc += rj.w * kernel_w<KERNEL, T>(q, C.sigma);
+                              });
+    rho_out[i] = acc;
+    if (with_eos) {
+        const T p = tait<T>(acc, C);
+        p_out[i] = p;
+        typename Vec2<T>::type v2;
+        v2.x = acc;
+        v2.y = p / (acc * acc);
+        rp[i] = v2;
+    }
+}
+
+// Momentum equation for fluid particles (walls: a = 0):
+//   a_i = g + sum_{j != i} m_j [ -(P_i + P_j) F r_ij
+//                               + 4 nu/(rho_i+rho_j) F |r|^2/(|r|^2 + eta h^2) v_ij ]
+// with F = (dW/dr)/r.  kick = 1 also closes the step: u = v + dt/2 a (FP64).
+template <int DIM, int KERNEL, typename T>
+__global__ __launch_bounds__(kBlock) void k_momentum(int n, Grid G, PairConst<T> C,
+                                                     const uint32_t* __restrict__ skey,
+                                                     const typename Vec4<T>::type* __restrict__ pos,
+                                                     const typename Vec4<T>::type* __restrict__ vel,
+                                                     const typename Vec2<T>::type* __restrict__ rp,
+                                                     const uint8_t* __restrict__ type,
+                                                     const uint32_t* __restrict__ cstart,
+                                                     const uint32_t* __restrict__ cend, State S,
+                                                     int kick, double hdt) {
+    const int i = xcd_block() * kBlock + threadIdx.x;
+    if (i >= n) return;
+    T* a0 = (T*)S.a[0];
+    T* a1 = (T*)S.a[1];
+    T* a2 = (T*)S.a[2];
+    if (type[i] != 0) {
+        a0[i] = T(0);
+        a1[i] = T(0);
+        if (DIM == 3) a2[i] = T(0);
+        if (kick) {
+            S.u[0][i] = 0.0;
+            S.u[1][i] = 0.0;
+            if (DIM == 3) S.u[2][i] = 0.0;
+        }
+        return;
+    }
+    const typename Vec4<T>::type ri = pos[i];
+    const typename Vec4<T>::type vi = vel[i];
+    const typename Vec2<T>::type rpi = rp[i];
+    T ax = C.g[0], ay = C.g[1], az = C.g[2];
+    for_each_neighbor<DIM, T>(
+        G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
+        [&](uint32_t j, const typename Vec4<T>::type& rj, T dx, T dy, T dz, T r2) {
+            if (j == (uint32_t)i) return;
+            const typename Vec4<T>::type vj = vel[j];
+            const typename Vec2<T>::type rpj = rp[j];
+            const T q = p_sqrt(r2) * C.inv_h;
+            const T F = kernel_f<KERNEL, T>(q, C.sigma_h2);
+            const T pres = -(rpi.y + rpj.y) * F;
+            const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
+            const T mj = rj.w;
+            ax += mj * (pres * dx + visc * (vi.x - vj.x));
+            ay += mj * (pres * dy + visc * (vi.y - vj.y));
+            if (DIM == 3) az += mj * (pres * dz + visc * (vi.z - vj.z));
+        });
+    a0[i] = ax;
+    a1[i] = ay;
+    if (DIM == 3) a2[i] = az;
+    if (kick) {
+#pragma clang fp contract(off)
+        S.u[0][i] = S.u[0][i] + hdt * (double)ax;
+        S.u[1][i] = S.u[1][i] + hdt * (double)ay;
+        if (DIM == 3) S.u[2][i] = S.u[2][i] + hdt * (double)az;
+    }
+}
+
+// Neighbour counts (phase 1) and lists (phase 2) of sph_neighbors.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_count(int n, Grid G, PairConst<T> C,
+                                                      const uint32_t* __restrict__ skey,
+                                                      const typename Vec4<T>::type* __restrict__ pos,
+                                                      const uint32_t* __restrict__ cstart,
+                                                      const uint32_t* __restrict__ cend,
+                                                      uint32_t* __restrict__ cnt) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const typename Vec4<T>::type ri = pos[i];
+    uint32_t c = 0;
+    for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
+                              [&](uint32_t, const typename Vec4<T>::type&, T, T, T, T) { ++c; });
+    cnt[i] = c;
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_nbr_fill(int n, Grid G, PairConst<T> C,
+                                                     const uint32_t* __restrict__ skey,
+                                                     const typename Vec4<T>::type* __restrict__ pos,
+                                                     const uint32_t* __restrict__ cstart,
+                                                     const uint32_t* __restrict__ cend,
+                                                     const int64_t* __restrict__ off,
+                                                     int32_t* __restrict__ nbr) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const typename Vec4<T>::type ri = pos[i];
+    int64_t w = off[i];
+    const int64_t wend = off[i + 1];
+    for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
+                              [&](uint32_t j, const typename Vec4<T>::type&, T, T, T, T) {
+                                  if (w < wend) nbr[w++] = (int32_t)j;
+                              });
+}
+
+// Tait EOS alone (sph_eos).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_eos(int n, PairConst<T> C, const T* __restrict__ rho,
+                                                T* __restrict__ p) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    p[i] = tait<T>(rho[i], C);
+}
+
+// Fill with a constant (used instead of a memset so the sequence can be
+// captured into a graph).
+__global__ __launch_bounds__(kBlock) void k_fill_u32(int64_t len, uint32_t v,
+                                                     uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) out[i] = v;
+}
+
+// cell_start / cell_end from the scanned offsets.
+__global__ __launch_bounds__(kBlock) void k_cell_ranges(int64_t ncells,
+                                                        const uint32_t* __restrict__ start,
+                                                        uint32_t* __restrict__ cs,
+                                                        uint32_t* __restrict__ ce) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncells) return;
+    cs[c] = start[c];
+    ce[c] = start[c + 1];
+}
+
+// Copy a state (all fields) slot by slot.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_state(int n, State src, State dst) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int q = 0; q < DIM; ++q) {
+        dst.x[q][i] = src.x[q][i];
+        dst.u[q][i] = src.u[q][i];
+        ((T*)dst.a[q])[i] = ((const T*)src.a[q])[i];
+    }
+    dst.m[i] = src.m[i];
+    dst.type[i] = src.type[i];
+    dst.id[i] = src.id[i];
+    ((T*)dst.rho)[i] = ((const T*)src.rho)[i];
+    ((T*)dst.p)[i] = ((const T*)src.p)[i];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics: KE = sum m |u|^2 / 2 and momentum sum m u, as fixed-order
+// tree sums (per-block partials, then one block over the partials).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_diag_partial(int n, State S,
+                                                         double* __restrict__ part) {
+    __shared__ double sh[4][kBlock];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < n) {
+        const double m = S.m[i];
+        double u2 = 0.0;
+        for (int q = 0; q < DIM; ++q) {
+            const double u = S.u[q][i];
+            u2 += u * u;
+            v[1 + q] = m * u;
+        }
+        v[0] = 0.5 * m * u2;
+    }
+    for (int q = 0; q < 1 + DIM; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 1 + DIM; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 1 + DIM; ++q) part[(int64_t)q * gridDim.x + blockIdx.x] = sh[q][0];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_diag_final(int nparts, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    __shared__ double sh[4][kBlock];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += kBlock)
+        for (int q = 0; q < 1 + DIM; ++q) v[q] += part[(int64_t)q * nparts + b];
+    for (int q = 0; q < 1 + DIM; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 1 + DIM; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 1 + DIM; ++q) out[q] = sh[q][0];
+}
+
+}  // namespace sph

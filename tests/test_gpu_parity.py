@@ -1,0 +1,253 @@
+"""GPU parity: every C-ABI entry point of the gfx950 library against the FP64
+CPU oracle on the same seeded inputs.
+
+Bars: bit-exact for the sort, the permutation, the cell ranges and the
+neighbour sets; FP64 fields within 1e-12 normwise (max |gpu - ref| / max |ref|
+per component); mixed precision within 1e-5 for density and 1e-4 for
+acceleration.  Fixtures for set comparisons drop particles that have a
+neighbour within a relative 1e-5 of the support radius (well-posed sets)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1909_04504_amd as sph
+import sph_workloads as W
+from helpers import drop_near_ties, normwise, order_by_id, shuffled
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [sph.FP64, sph.FP32_MIXED]
+TOL_RHO = {sph.FP64: 1e-12, sph.FP32_MIXED: 1e-5}
+TOL_ACC = {sph.FP64: 1e-12, sph.FP32_MIXED: 1e-4}
+
+
+def make_case(name):
+    if name == "tg2d":
+        return W.taylor_green(50, jitter=0.3, seed=11)
+    if name == "tg2d_cd2":
+        return W.taylor_green(50, jitter=0.3, seed=12, cell_div=2)
+    if name == "cube3d":
+        return W.periodic_cube(n_side=14, jitter=0.3, sigma_u=0.1, seed=13)
+    if name == "cube3d_cd2":
+        return W.periodic_cube(n_side=14, jitter=0.3, sigma_u=0.1, seed=14, cell_div=2)
+    if name == "dam3d":
+        p, s = W.dam_break_3d(dx=0.04)
+        rng = np.random.default_rng(15)
+        s.u[:, s.ptype == 0] = rng.normal(0, 0.3, size=(3, int((s.ptype == 0).sum())))
+        return p, s
+    if name == "box2d":
+        # non-periodic 2D box with gravity, cubic spline
+        p, s = W.taylor_green(40, jitter=0.3, seed=16)
+        p = p.replace(periodic=(0, 0, 0), lo=(-0.05, -0.05, 0), hi=(1.05, 1.05, 0),
+                      g=(0.0, -9.81, 0.0))
+        s.ptype[: s.n // 10] = W.WALL
+        s.u[:, : s.n // 10] = 0
+        return p, s
+    raise KeyError(name)
+
+
+CASES = ["tg2d", "tg2d_cd2", "cube3d", "cube3d_cd2", "dam3d", "box2d"]
+
+
+def gpu_sorted(p, s, prec):
+    prm = sph.make_params(p, prec)
+    dp = sph.DeviceParticles.from_state(s, prec)
+    ws = sph.workspace(prm, s.n)
+    cs, ce = sph.cell_arrays(prm)
+    sph.bin_sort(prm, dp, ws, cs, ce)
+    return prm, dp, ws, cs, ce
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_bin_sort_bit_exact(case):
+    p, s = make_case(case)
+    s = shuffled(s, seed=1)
+    keys, perm, cs_ref, ce_ref = oracle.bin_sort(p, s.x)
+    for prec in PRECS:
+        prm, dp, ws, cs, ce = gpu_sorted(p, s, prec)
+        out = dp.numpy()
+        assert np.array_equal(out["id"], s.pid[perm])
+        assert np.array_equal(out["x"], s.x[:, perm])
+        assert np.array_equal(out["u"], s.u[:, perm])
+        assert np.array_equal(out["m"], s.m[perm])
+        assert np.array_equal(out["type"], s.ptype[perm])
+        assert np.array_equal(cs.cpu().numpy().view(np.uint32), cs_ref)
+        assert np.array_equal(ce.cpu().numpy().view(np.uint32), ce_ref)
+        sph.check(ws)
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("prec", PRECS)
+def test_neighbor_sets_bit_exact(case, prec):
+    p, s = make_case(case)
+    s = drop_near_ties(p, s, 1e-5)
+    s = shuffled(s, seed=2)
+    prm, dp, ws, cs, ce = gpu_sorted(p, s, prec)
+    n = s.n
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(sph.SphError) as ei:
+        sph.neighbors(prm, dp, cs, ce, 0, offsets, None, ws)
+    assert ei.value.code == sph.SPH_ECAPACITY
+    total = ei.value.total
+    nbr = torch.zeros(total, dtype=torch.int32, device="cuda")
+    assert sph.neighbors(prm, dp, cs, ce, total, offsets, nbr, ws) == total
+    off = offsets.cpu().numpy()
+    idx = nbr.cpu().numpy()
+    ids = dp.id.cpu().numpy()
+    xs = dp.x.cpu().numpy()
+    ro, ri = oracle.neighbors(p, xs, brute=s.n <= 4096)
+    assert np.array_equal(off, ro)
+    for i in range(n):
+        got = np.sort(idx[off[i]:off[i + 1]])
+        assert np.array_equal(got, ri[ro[i]:ro[i + 1]]), f"row {i} (id {ids[i]})"
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("prec", PRECS)
+def test_density_eos_momentum_parity(case, prec):
+    """Standalone density, EOS and momentum calls on a sorted state."""
+    p, s = make_case(case)
+    s = drop_near_ties(p, s, 1e-5)
+    s = shuffled(s, seed=3)
+    prm, dp, ws, cs, ce = gpu_sorted(p, s, prec)
+    sph.density(prm, dp, cs, ce, ws)
+    sph.eos(prm, dp)
+    sph.momentum(prm, dp, cs, ce, ws)
+    out = dp.numpy()
+    rho, pr, a = oracle.evaluate(p, out["x"], out["u"], out["m"], out["type"])
+    assert normwise(out["rho"], rho) < TOL_RHO[prec]
+    # p is a difference of nearly equal terms: its error is measured against
+    # the pressure scale B = rho0 c0^2 / 7
+    B = p.rho0 * p.c0 ** 2 / 7
+    assert np.abs(out["p"] - pr).max() / B < 7 * TOL_RHO[prec] * 4
+    assert normwise(out["a"], a) < TOL_ACC[prec]
+    sph.check(ws)
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_prime_evaluation(case, prec):
+    """sph_step with prime and zero steps: the fused density+EOS and momentum
+    kernels at the input state, particles left sorted."""
+    p, s = make_case(case)
+    s = drop_near_ties(p, s, 1e-5)
+    prm = sph.make_params(p, prec)
+    dp = sph.DeviceParticles.from_state(shuffled(s, 4), prec)
+    ws = sph.workspace(prm, s.n)
+    sph.step(prm, dp, 0, ws, prime=True)
+    out = dp.numpy()
+    rho, pr, a = oracle.evaluate(p, out["x"], out["u"], out["m"], out["type"])
+    assert normwise(out["rho"], rho) < TOL_RHO[prec]
+    assert normwise(out["a"], a) < TOL_ACC[prec]
+    keys = oracle.cell_keys(p, out["x"])
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0)
+
+
+def test_taylor_green_64_trajectory_fp64():
+    """50 FP64 predictor-corrector steps of the 64x64 Taylor-Green vortex:
+    every field within 1e-12 of the oracle, matched by id."""
+    wl = W.workload("tg64")
+    p, s = wl.params, wl.state
+    ref = oracle.step(p, s.x, s.u, s.m, s.ptype, wl.steps, want_diag=True)
+    prm = sph.make_params(p, sph.FP64)
+    dp = sph.DeviceParticles.from_state(s, sph.FP64)
+    ws = sph.workspace(prm, s.n)
+    diag = torch.zeros((wl.steps, 3), dtype=torch.float64, device="cuda")
+    sph.step(prm, dp, wl.steps, ws, prime=True, diag=diag)
+    out = dp.numpy()
+    o = order_by_id(out["id"])
+    dx = out["x"][:, o] - ref["x"]
+    dx -= np.round(dx)
+    assert np.abs(dx).max() < 1e-12
+    for f in ("u", "a"):
+        assert normwise(out[f][:, o], ref[f]) < 1e-12, f
+    for f in ("rho", "p"):
+        assert np.abs(out[f][o] - ref[f]).max() < 1e-12 * max(1.0, np.abs(ref[f]).max()), f
+    d = diag.cpu().numpy()
+    assert np.abs(d[:, 0] / ref["diag"][:, 0] - 1).max() < 1e-12
+    assert np.abs(d[:, 1:] - ref["diag"][:, 1:]).max() < 1e-12 * 0.25
+    sph.check(ws)
+
+
+@pytest.mark.parametrize("case", ["tg2d", "cube3d", "dam3d"])
+def test_mixed_precision_few_steps(case):
+    p, s = make_case(case)
+    nsteps = 5
+    ref = oracle.step(p, s.x, s.u, s.m, s.ptype, nsteps)
+    prm = sph.make_params(p, sph.FP32_MIXED)
+    dp = sph.DeviceParticles.from_state(s, sph.FP32_MIXED)
+    ws = sph.workspace(prm, s.n)
+    sph.step(prm, dp, nsteps, ws, prime=True)
+    out = dp.numpy()
+    o = order_by_id(out["id"])
+    assert normwise(out["rho"][o], ref["rho"]) < 1e-5
+    assert normwise(out["a"][:, o], ref["a"]) < 2e-4
+    assert normwise(out["u"][:, o], ref["u"]) < 1e-5
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_bitwise_deterministic(prec):
+    p, s = make_case("cube3d")
+    outs = []
+    for _ in range(2):
+        prm = sph.make_params(p, prec)
+        dp = sph.DeviceParticles.from_state(s, prec)
+        ws = sph.workspace(prm, s.n)
+        sph.step(prm, dp, 10, ws, prime=True)
+        outs.append(dp.numpy())
+    for f in outs[0]:
+        assert np.array_equal(outs[0][f], outs[1][f]), f
+
+
+def test_check_reports_nonfinite_and_outside():
+    p, s = make_case("box2d")
+    s.x[0, 5] = np.nan
+    prm = sph.make_params(p, sph.FP64)
+    dp = sph.DeviceParticles.from_state(s, sph.FP64)
+    ws = sph.workspace(prm, s.n)
+    cs, ce = sph.cell_arrays(prm)
+    sph.bin_sort(prm, dp, ws, cs, ce)
+    with pytest.raises(sph.SphError) as ei:
+        sph.check(ws)
+    assert ei.value.code == sph.SPH_ENONFINITE
+    sph.check(ws)  # cleared
+    p2, s2 = make_case("box2d")
+    s2.x[1, 7] = 2.0  # above hi = 1.05 on a non-periodic axis
+    dp2 = sph.DeviceParticles.from_state(s2, sph.FP64)
+    sph.bin_sort(prm, dp2, ws, cs, ce)
+    with pytest.raises(sph.SphError) as ei:
+        sph.check(ws)
+    assert ei.value.code == sph.SPH_EDOMAIN
+
+
+def test_single_particle_and_one_cell():
+    """Degenerate inputs: one particle (rho = m W(0), a = g); every particle
+    inside one cell."""
+    p = W.Params(dim=2, kernel=W.CUBIC, h=0.1, rho0=1.0, c0=10.0, nu=0.01, eta=0.01, dt=1e-3,
+                 g=(0.0, -1.0, 0.0), lo=(0, 0, 0), hi=(1, 1, 0), periodic=(0, 0, 0))
+    s = W.State(np.array([[0.5], [0.5]]), np.zeros((2, 1)), np.array([0.01]),
+                np.zeros(1, np.uint8), np.zeros(1, np.int32))
+    for prec in PRECS:
+        prm = sph.make_params(p, prec)
+        dp = sph.DeviceParticles.from_state(s, prec)
+        ws = sph.workspace(prm, 1)
+        sph.step(prm, dp, 0, ws, prime=True)
+        out = dp.numpy()
+        rho, _, a = oracle.evaluate(p, s.x, s.u, s.m, s.ptype)
+        assert normwise(out["rho"], rho) < TOL_RHO[prec]
+        assert np.array_equal(out["a"][:, 0].astype(np.float64), np.array([0.0, -1.0]))
+    rng = np.random.default_rng(5)
+    n = 300
+    x = 0.5 + rng.uniform(-0.04, 0.04, size=(2, n))
+    s = W.State(x, rng.normal(0, 0.1, (2, n)), np.full(n, 1e-4), np.zeros(n, np.uint8),
+                np.arange(n, dtype=np.int32))
+    for prec in PRECS:
+        prm = sph.make_params(p, prec)
+        dp = sph.DeviceParticles.from_state(s, prec)
+        ws = sph.workspace(prm, n)
+        sph.step(prm, dp, 0, ws, prime=True)
+        out = dp.numpy()
+        rho, _, a = oracle.evaluate(p, out["x"], out["u"], out["m"], out["type"])
+        assert normwise(out["rho"], rho) < TOL_RHO[prec]
+        assert normwise(out["a"], a) < TOL_ACC[prec]
