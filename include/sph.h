@@ -171,10 +171,28 @@ int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t 
 /* Adjoint of the acceleration evaluation a = A(x, u; nu) at the state `st`
  * (sorted or not): given lam_a (dim arrays of n doubles), ADDS (dA/dx)^T lam_a
  * to lam_x, (dA/du)^T lam_a to lam_u and (dA/dnu)^T lam_a to *dJ_dnu.
- * Arrays in the order of st.  st is not modified. */
+ * Arrays in the order of st.  st is not modified.  The workspace must be
+ * sized with adjoint_k >= 1. */
 int sph_accel_backward(const sph_params* prm, const sph_particles* st, const double* lam_a,
                        double* lam_x, double* lam_u, double* dJ_dnu, void* ws, size_t ws_bytes,
                        void* stream);
+
+/* Interaction count (the throughput metric's unit): every density evaluation
+ * (sph_density and each evaluation inside sph_step) adds sum_i |N(i)| (ordered
+ * pairs, each particle counted as its own neighbour) to a 64-bit counter in
+ * the workspace.  Synchronises the stream, stores the counter in *total
+ * (host), and zeroes it if reset = 1. */
+int sph_read_interactions(void* ws, size_t ws_bytes, int64_t* total, int reset, void* stream);
+
+/* Per-kernel timing for benchmarks.  While enabled (on = 1), each kernel
+ * launch of the library is bracketed by two HIP events recorded on the call's
+ * stream.  sph_timer_read synchronises on those events and, for each kernel
+ * slot k < nslots, stores its name (static string), the summed elapsed
+ * milliseconds and the number of launches; reset = 1 then clears the totals.
+ * Returns the number of kernel slots.  Process-wide state, not thread-safe;
+ * keep it disabled while a stream is being captured into a graph. */
+int sph_timer_enable(int on);
+int sph_timer_read(int nslots, const char** names, double* ms, int64_t* launches, int reset);
 
 /* Synchronises the stream and returns SPH_OK, or the first device-detected
  * condition since the last call (SPH_ENONFINITE, then SPH_EDOMAIN), and

@@ -48,7 +48,8 @@ class Particles(ctypes.Structure):
 
 EXPORTED = ("sph_grid", "sph_workspace_bytes", "sph_bin_sort", "sph_neighbors", "sph_density",
             "sph_eos", "sph_momentum", "sph_step", "sph_step_backward", "sph_accel_backward",
-            "sph_check", "sph_last_error")
+            "sph_check", "sph_last_error", "sph_read_interactions", "sph_timer_enable",
+            "sph_timer_read")
 
 _lib = None
 
@@ -74,6 +75,9 @@ def lib():
         L.sph_step_backward.argtypes = [_P, _P, _i64, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_accel_backward.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_check.argtypes = [_P, ctypes.c_size_t, _P]
+        L.sph_read_interactions.argtypes = [_P, ctypes.c_size_t, _P, ctypes.c_int, _P]
+        L.sph_timer_enable.argtypes = [ctypes.c_int]
+        L.sph_timer_read.argtypes = [ctypes.c_int, _P, _P, _P, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -99,22 +103,29 @@ def pair_dtype(precision: int) -> torch.dtype:
     return torch.float64 if precision == FP64 else torch.float32
 
 
+def _dev(v, dtype, device) -> torch.Tensor:
+    """A contiguous device tensor copy of a numpy array or tensor."""
+    if torch.is_tensor(v):
+        return v.detach().to(device=device, dtype=dtype).contiguous().clone()
+    return torch.as_tensor(np.ascontiguousarray(v)).to(device=device, dtype=dtype)
+
+
 class DeviceParticles:
     """Device arrays of one particle set (SoA; vectors as (dim, n) tensors)."""
 
     def __init__(self, x, u, m, ptype, pid, precision: int = FP64, a=None, device="cuda"):
         T = pair_dtype(precision)
         self.precision = precision
-        self.x = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).to(device)
-        self.u = torch.as_tensor(np.ascontiguousarray(u), dtype=torch.float64).to(device)
+        self.x = _dev(x, torch.float64, device)
+        self.u = _dev(u, torch.float64, device)
         self.dim, self.n = self.x.shape
         self.a = (torch.zeros((self.dim, self.n), dtype=T, device=device) if a is None else
-                  torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=T))
+                  _dev(a, T, device))
         self.rho = torch.zeros(self.n, dtype=T, device=device)
         self.p = torch.zeros(self.n, dtype=T, device=device)
-        self.m = torch.as_tensor(np.ascontiguousarray(m), dtype=torch.float64).to(device)
-        self.type = torch.as_tensor(np.ascontiguousarray(ptype), dtype=torch.uint8).to(device)
-        self.id = torch.as_tensor(np.ascontiguousarray(pid), dtype=torch.int32).to(device)
+        self.m = _dev(m, torch.float64, device)
+        self.type = _dev(ptype, torch.uint8, device)
+        self.id = _dev(pid, torch.int32, device)
 
     @classmethod
     def from_state(cls, s, precision: int = FP64, device="cuda"):
@@ -239,3 +250,25 @@ def accel_backward(prm, st: DeviceParticles, lam_a, lam_x, lam_u, dJ_dnu, ws, st
 
 def check(ws, stream=None):
     _rc(lib().sph_check(ws.data_ptr(), ws.numel(), _stream(stream)))
+
+
+def read_interactions(ws, reset: bool = True, stream=None) -> int:
+    """Total interactions sum_i |N(i)| accumulated by density evaluations."""
+    t = ctypes.c_int64()
+    _rc(lib().sph_read_interactions(ws.data_ptr(), ws.numel(), ctypes.byref(t),
+                                    1 if reset else 0, _stream(stream)))
+    return t.value
+
+
+def timer_enable(on: bool = True):
+    _rc(lib().sph_timer_enable(1 if on else 0))
+
+
+def timer_read(reset: bool = True) -> dict:
+    """{kernel name: (total ms, launches)} of the launches timed so far."""
+    k = 32
+    names = (ctypes.c_char_p * k)()
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
+    n = lib().sph_timer_read(k, names, ms, cnt, 1 if reset else 0)
+    return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(n, k)) if cnt[i] > 0}

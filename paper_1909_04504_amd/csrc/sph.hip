@@ -7,9 +7,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "sph.h"
 #include "sph_kernels.hpp"
+#include "sph_adjoint.hpp"
 
 namespace {
 
@@ -44,6 +46,71 @@ inline int launch_check(const char* what) {
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + sph::kBlock - 1) / sph::kBlock); }
+
+// ---------------------------------------------------------------------------
+// Opt-in per-kernel event timing (benchmark instrumentation)
+
+enum KernelId {
+    K_FILL, K_HASH, K_CHUNK_SUM, K_CHUNK_SCAN, K_SCATTER, K_RANK_GATHER, K_PACK, K_DENSITY,
+    K_MOMENTUM, K_EOS, K_NBR_COUNT, K_NBR_FILL, K_CELL_RANGES, K_COPY, K_DIAG, K_ADJ_SEED,
+    K_ADJ_PAIR1, K_ADJ_PAIR2, K_ADJ_REDUCE, K_ADJ_KICK, K_COUNT
+};
+const char* const kKernelNames[K_COUNT] = {
+    "fill", "drift_hash", "chunk_sum", "chunk_scan", "scatter", "rank_gather", "pack",
+    "density", "momentum", "eos", "nbr_count", "nbr_fill", "cell_ranges", "copy_state", "diag",
+    "adj_seed", "adj_pair1", "adj_pair2", "adj_reduce", "adj_kick"};
+
+struct Timer {
+    bool on = false;
+    struct Pending { int id; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;
+    double ms[K_COUNT] = {};
+    int64_t launches[K_COUNT] = {};
+
+    hipEvent_t get() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void fold() {
+        for (const Pending& q : pending) {
+            float t = 0.f;
+            if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&t, q.a, q.b) == hipSuccess) {
+                ms[q.id] += t;
+                launches[q.id] += 1;
+            }
+            spare.push_back(q.a);
+            spare.push_back(q.b);
+        }
+        pending.clear();
+    }
+};
+Timer g_timer;
+
+// Brackets one launch with events on the launch stream while timing is on.
+struct Timed {
+    int id;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(int id_, hipStream_t st_) : id(id_), st(st_) {
+        if (!g_timer.on) return;
+        a = g_timer.get();
+        b = g_timer.get();
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    ~Timed() {
+        if (!g_timer.on || !a || !b) return;
+        (void)hipEventRecord(b, st);
+        g_timer.pending.push_back({id, a, b});
+        if (g_timer.pending.size() > 200000) g_timer.fold();
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Validation
@@ -123,17 +190,32 @@ int check_particles(const sph_params* p, const sph_particles* pa) {
 // ---------------------------------------------------------------------------
 // Workspace layout (all offsets 256-byte aligned)
 
+struct StateOff {
+    size_t x, u, a, m, type, id, rho, p;
+};
+
+// One recompute-tape slot: the pair records and sort results of one step.
+struct SlotOff {
+    size_t pos, vel, rp, skey, perm, type, start;
+};
+
 struct Layout {
     size_t flags, counts, start, chunks, key, tmp, perm, skey, ncnt;
-    size_t sx, su, sa, sm, stype, sid, srho, sp;
+    StateOff s1, s2;
     size_t pos, vel, rp, diag;
+    // adjoint (present when adj_k > 0; the tape is the last region)
+    int64_t adj_k;
+    size_t lamB, lamC, lhat, lxd, lvd, lrho, nupart;
+    SlotOff slot;
+    size_t slot_bytes, tape;
     size_t bytes;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Layout make_layout(const sph_params* p, int64_t n, int64_t ncells) {
+Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k) {
     Layout L;
+    std::memset(&L, 0, sizeof L);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -142,6 +224,18 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells) {
     };
     const size_t T = p->precision == SPH_FP64 ? 8 : 4;
     const size_t d = (size_t)p->dim, N = (size_t)n;
+    auto take_state = [&]() {
+        StateOff so;
+        so.x = take(8 * d * N);
+        so.u = take(8 * d * N);
+        so.a = take(T * d * N);
+        so.m = take(8 * N);
+        so.type = take(N);
+        so.id = take(4 * N);
+        so.rho = take(T * N);
+        so.p = take(T * N);
+        return so;
+    };
     const int64_t longest = (ncells + 1 > n + 1) ? ncells + 1 : n + 1;
     const size_t nchunks = (size_t)((longest + sph::kScanChunk - 1) / sph::kScanChunk);
     L.flags = take(256);
@@ -153,18 +247,37 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells) {
     L.perm = take(4 * N);
     L.skey = take(4 * N);
     L.ncnt = take(4 * N);
-    L.sx = take(8 * d * N);
-    L.su = take(8 * d * N);
-    L.sa = take(T * d * N);
-    L.sm = take(8 * N);
-    L.stype = take(N);
-    L.sid = take(4 * N);
-    L.srho = take(T * N);
-    L.sp = take(T * N);
+    L.s1 = take_state();
     L.pos = take(4 * T * N);
     L.vel = take(4 * T * N);
     L.rp = take(2 * T * N);
     L.diag = take(8 * 4 * (size_t)blocks_for(n));
+    L.adj_k = adj_k;
+    if (adj_k > 0) {
+        L.s2 = take_state();
+        L.lamB = take(8 * 3 * d * N);
+        L.lamC = take(8 * 3 * d * N);
+        L.lhat = take(4 * T * N);
+        L.lxd = take(8 * d * N);
+        L.lvd = take(8 * d * N);
+        L.lrho = take(T * N);
+        L.nupart = take(8 * N);
+        size_t so = 0;
+        auto slot_take = [&](size_t bytes) {
+            const size_t o = so;
+            so = align256(so + bytes);
+            return o;
+        };
+        L.slot.pos = slot_take(4 * T * N);
+        L.slot.vel = slot_take(4 * T * N);
+        L.slot.rp = slot_take(2 * T * N);
+        L.slot.skey = slot_take(4 * N);
+        L.slot.perm = slot_take(4 * N);
+        L.slot.type = slot_take(N);
+        L.slot.start = slot_take(4 * ((size_t)ncells + 1));
+        L.slot_bytes = so;
+        L.tape = take(L.slot_bytes * (size_t)adj_k);
+    }
     L.bytes = off;
     return L;
 }
@@ -184,20 +297,20 @@ sph::State user_state(const sph_particles* pa) {
     return s;
 }
 
-sph::State ws_state(char* ws, const Layout& L, const sph_params* p, int64_t n) {
+sph::State ws_state(char* ws, const StateOff& L, const sph_params* p, int64_t n) {
     const size_t T = p->precision == SPH_FP64 ? 8 : 4;
     sph::State s;
     for (int k = 0; k < 3; ++k) {
         const bool used = k < p->dim;
-        s.x[k] = used ? (double*)(ws + L.sx) + k * n : nullptr;
-        s.u[k] = used ? (double*)(ws + L.su) + k * n : nullptr;
-        s.a[k] = used ? (void*)(ws + L.sa + T * k * n) : nullptr;
+        s.x[k] = used ? (double*)(ws + L.x) + k * n : nullptr;
+        s.u[k] = used ? (double*)(ws + L.u) + k * n : nullptr;
+        s.a[k] = used ? (void*)(ws + L.a + T * k * n) : nullptr;
     }
-    s.rho = ws + L.srho;
-    s.p = ws + L.sp;
-    s.m = (double*)(ws + L.sm);
-    s.type = (uint8_t*)(ws + L.stype);
-    s.id = (int32_t*)(ws + L.sid);
+    s.rho = ws + L.rho;
+    s.p = ws + L.p;
+    s.m = (double*)(ws + L.m);
+    s.type = (uint8_t*)(ws + L.type);
+    s.id = (int32_t*)(ws + L.id);
     return s;
 }
 
@@ -224,6 +337,8 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
     C.rho0 = (T)p->rho0;
     C.inv_rho0 = (T)(1.0 / p->rho0);
     C.B = (T)(p->rho0 * p->c0 * p->c0 / 7.0);
+    C.sigma_h4 = (T)(sigma / (h * h * h * h));
+    C.b7 = (T)(p->c0 * p->c0);  // 7 B / rho0 = c0^2
     return C;
 }
 
@@ -244,19 +359,51 @@ struct Engine {
     sph::PairConst<T> C;
 
     uint32_t* flags() const { return (uint32_t*)(ws + L.flags); }
+    unsigned long long* pairs() const { return (unsigned long long*)(ws + L.flags + 8); }
     uint32_t* counts() const { return (uint32_t*)(ws + L.counts); }
-    uint32_t* start() const { return (uint32_t*)(ws + L.start); }
     uint64_t* chunks() const { return (uint64_t*)(ws + L.chunks); }
     uint32_t* key() const { return (uint32_t*)(ws + L.key); }
     uint32_t* tmp() const { return (uint32_t*)(ws + L.tmp); }
-    uint32_t* perm() const { return (uint32_t*)(ws + L.perm); }
-    uint32_t* skey() const { return (uint32_t*)(ws + L.skey); }
     uint32_t* ncnt() const { return (uint32_t*)(ws + L.ncnt); }
-    V4* pos() const { return (V4*)(ws + L.pos); }
-    V4* vel() const { return (V4*)(ws + L.vel); }
-    V2* rp() const { return (V2*)(ws + L.rp); }
+
+    // Pair records and sort results of the current evaluation: the default
+    // buffers, or one slot of the adjoint's recompute tape.
+    V4* posp = nullptr;
+    V4* velp = nullptr;
+    V2* rpp = nullptr;
+    uint32_t* skeyp = nullptr;
+    uint32_t* permp = nullptr;
+    uint32_t* startp = nullptr;
+    uint8_t* typetape = nullptr;
+    uint32_t* perm() const { return permp; }
+    uint32_t* skey() const { return skeyp; }
+    uint32_t* start() const { return startp; }
+    V4* pos() const { return posp; }
+    V4* vel() const { return velp; }
+    V2* rp() const { return rpp; }
+
+    void default_records() {
+        posp = (V4*)(ws + L.pos);
+        velp = (V4*)(ws + L.vel);
+        rpp = (V2*)(ws + L.rp);
+        skeyp = (uint32_t*)(ws + L.skey);
+        permp = (uint32_t*)(ws + L.perm);
+        startp = (uint32_t*)(ws + L.start);
+        typetape = nullptr;
+    }
+    void tape_records(int64_t slot) {
+        char* b = ws + L.tape + (size_t)slot * L.slot_bytes;
+        posp = (V4*)(b + L.slot.pos);
+        velp = (V4*)(b + L.slot.vel);
+        rpp = (V2*)(b + L.slot.rp);
+        skeyp = (uint32_t*)(b + L.slot.skey);
+        permp = (uint32_t*)(b + L.slot.perm);
+        typetape = (uint8_t*)(b + L.slot.type);
+        startp = (uint32_t*)(b + L.slot.start);
+    }
 
     int zero_counts() {
+        Timed t_(K_FILL, st);
         sph::k_fill_u32<<<blocks_for(ncells), sph::kBlock, 0, st>>>(ncells, 0u, counts());
         return launch_check("k_fill_u32");
     }
@@ -265,8 +412,12 @@ struct Engine {
     template <typename OUT>
     int scan(const uint32_t* in, int64_t len, OUT* out) {
         const unsigned nch = (unsigned)((len + sph::kScanChunk - 1) / sph::kScanChunk);
+        {
+        Timed t_(K_CHUNK_SUM, st);
         sph::k_chunk_sum<<<nch, sph::kBlock, 0, st>>>(in, len, chunks());
         SPH_TRY(launch_check("k_chunk_sum"));
+        }
+        Timed t_(K_CHUNK_SCAN, st);
         sph::k_chunk_scan<OUT><<<nch, sph::kBlock, 0, st>>>(in, len, chunks(), out);
         return launch_check("k_chunk_scan");
     }
@@ -276,37 +427,48 @@ struct Engine {
     int sort_into(const sph::State& src, const sph::State& dst, bool drift, bool copy_derived) {
         const unsigned nb = blocks_for(n);
         using TA = T;
+        {
+        Timed t_(K_HASH, st);
         sph::k_drift_hash<DIM, TA><<<nb, sph::kBlock, 0, st>>>(n, src, G, 0.5 * prm->dt, prm->dt,
                                                               drift ? 1 : 0, key(), counts(), flags());
         SPH_TRY(launch_check("k_drift_hash"));
+        }
         SPH_TRY(scan<uint32_t>(counts(), ncells, start()));
+        {
+        Timed t_(K_SCATTER, st);
         sph::k_scatter<<<nb, sph::kBlock, 0, st>>>(n, key(), start(), counts(), tmp());
         SPH_TRY(launch_check("k_scatter"));
+        }
+        Timed t_(K_RANK_GATHER, st);
         sph::k_rank_gather<DIM, T><<<nb, sph::kBlock, 0, st>>>(n, tmp(), key(), start(), src, dst, G,
                                                              perm(), skey(), pos(), vel(),
-                                                             copy_derived ? 1 : 0);
+                                                             copy_derived ? 1 : 0, typetape);
         return launch_check("k_rank_gather");
     }
 
     int density(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_eos) {
+        Timed t_(K_DENSITY, st);
         sph::k_density<DIM, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
-            n, G, C, skey(), pos(), cs, ce, (T*)s.rho, (T*)s.p, rp(), with_eos ? 1 : 0);
+            n, G, C, skey(), pos(), cs, ce, (T*)s.rho, (T*)s.p, rp(), with_eos ? 1 : 0, pairs());
         return launch_check("k_density");
     }
 
     int momentum(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool kick) {
+        Timed t_(K_MOMENTUM, st);
         sph::k_momentum<DIM, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
             n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, s, kick ? 1 : 0, 0.5 * prm->dt);
         return launch_check("k_momentum");
     }
 
     int pack(const sph::State& s, bool with_rp) {
+        Timed t_(K_PACK, st);
         sph::k_pack<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, s, G, skey(), pos(), vel(),
                                                                   rp(), with_rp ? 1 : 0);
         return launch_check("k_pack");
     }
 
     int copy(const sph::State& src, const sph::State& dst) {
+        Timed t_(K_COPY, st);
         sph::k_copy_state<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, src, dst);
         return launch_check("k_copy_state");
     }
@@ -314,8 +476,12 @@ struct Engine {
     int diag(const sph::State& s, double* out) {
         const unsigned nb = blocks_for(n);
         double* part = (double*)(ws + L.diag);
+        {
+        Timed t_(K_DIAG, st);
         sph::k_diag_partial<DIM><<<nb, sph::kBlock, 0, st>>>(n, s, part);
         SPH_TRY(launch_check("k_diag_partial"));
+        }
+        Timed t_(K_DIAG, st);
         sph::k_diag_final<DIM><<<1, sph::kBlock, 0, st>>>((int)nb, part, out);
         return launch_check("k_diag_final");
     }
@@ -324,10 +490,11 @@ struct Engine {
 
     int bin_sort(sph_particles* pa, uint32_t* cs_out, uint32_t* ce_out) {
         const sph::State user = user_state(pa);
-        const sph::State tmp_state = ws_state(ws, L, prm, n);
+        const sph::State tmp_state = ws_state(ws, L.s1, prm, n);
         SPH_TRY(zero_counts());
         SPH_TRY(sort_into(user, tmp_state, false, true));
         SPH_TRY(copy(tmp_state, user));
+        Timed t_(K_CELL_RANGES, st);
         sph::k_cell_ranges<<<blocks_for(ncells), sph::kBlock, 0, st>>>(ncells, start(), cs_out, ce_out);
         return launch_check("k_cell_ranges");
     }
@@ -345,6 +512,7 @@ struct Engine {
     }
 
     int eos_only(sph_particles* pa) {
+        Timed t_(K_EOS, st);
         sph::k_eos<T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, C, (const T*)pa->rho, (T*)pa->p);
         return launch_check("k_eos");
     }
@@ -353,9 +521,12 @@ struct Engine {
                   int64_t* offsets, int32_t* nbr, int64_t* total) {
         const sph::State user = user_state(pa);
         SPH_TRY(pack(user, false));
+        {
+        Timed t_(K_NBR_COUNT, st);
         sph::k_nbr_count<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, G, C, skey(), pos(), cs,
                                                                        ce, ncnt());
         SPH_TRY(launch_check("k_nbr_count"));
+        }
         SPH_TRY(scan<int64_t>(ncnt(), n, offsets));
         int64_t tot = 0;
         SPH_HIP(hipMemcpyAsync(&tot, offsets + n, sizeof tot, hipMemcpyDeviceToHost, st));
@@ -365,6 +536,7 @@ struct Engine {
             return fail(SPH_ECAPACITY, "neighbour list needs %lld entries, capacity %lld",
                         (long long)tot, (long long)capacity);
         if (tot > 0 && !nbr) return fail(SPH_EINVAL, "nbr is NULL");
+        Timed t_(K_NBR_FILL, st);
         sph::k_nbr_fill<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, G, C, skey(), pos(), cs,
                                                                       ce, offsets, nbr);
         return launch_check("k_nbr_fill");
@@ -372,7 +544,7 @@ struct Engine {
 
     int step(sph_particles* pa, int64_t nsteps, int prime, double* diag_out) {
         const sph::State user = user_state(pa);
-        const sph::State wst = ws_state(ws, L, prm, n);
+        const sph::State wst = ws_state(ws, L.s1, prm, n);
         sph::State cur = user, nxt = wst;
         const uint32_t* cs = start();
         const uint32_t* ce = start() + 1;
@@ -393,6 +565,96 @@ struct Engine {
         if (cur.m != user.m) SPH_TRY(copy(cur, user));
         return SPH_OK;
     }
+
+    // (dA/dx)^T lhat -> lxd, (dA/dv)^T lhat -> lvd, (dA/dnu)^T lhat added to
+    // *dJ, at the evaluation whose records are current; lhat = lam_a +
+    // hdt lam_u (fluid), read through `gather` (identity if null).
+    int adjoint_rhs(const double* lam_u, const double* lam_a, int64_t ld, double hdt,
+                    const uint8_t* type, const uint32_t* gather, double* dJ) {
+        const unsigned nb = blocks_for(n);
+        V4* lhat = (V4*)(ws + L.lhat);
+        double* lxd = (double*)(ws + L.lxd);
+        double* lvd = (double*)(ws + L.lvd);
+        T* lrho = (T*)(ws + L.lrho);
+        double* nup = (double*)(ws + L.nupart);
+        double* part = (double*)(ws + L.diag);
+        {
+            Timed t_(K_ADJ_SEED, st);
+            sph::k_adj_seed<DIM, T><<<nb, sph::kBlock, 0, st>>>(n, lam_u, lam_a, ld, hdt, type,
+                                                               gather, lhat);
+            SPH_TRY(launch_check("k_adj_seed"));
+        }
+        {
+            Timed t_(K_ADJ_PAIR1, st);
+            sph::k_adj_pair1<DIM, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                n, G, C, skey(), pos(), vel(), rp(), lhat, start(), start() + 1, lxd, lvd, lrho,
+                nup);
+            SPH_TRY(launch_check("k_adj_pair1"));
+        }
+        {
+            Timed t_(K_ADJ_PAIR2, st);
+            sph::k_adj_pair2<DIM, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                n, G, C, skey(), pos(), lrho, start(), start() + 1, lxd);
+            SPH_TRY(launch_check("k_adj_pair2"));
+        }
+        Timed t_(K_ADJ_REDUCE, st);
+        sph::k_sum_partial<<<nb, sph::kBlock, 0, st>>>(n, nup, part);
+        SPH_TRY(launch_check("k_sum_partial"));
+        sph::k_sum_accum<<<1, sph::kBlock, 0, st>>>((int)nb, part, dJ);
+        return launch_check("k_sum_accum");
+    }
+
+    // k recomputed steps from the checkpoint, then their reverse.
+    int step_backward(const sph_particles* ck, int64_t k, const double* lam_in, double* lam_out,
+                      double* dJ) {
+        const sph::State user = user_state(ck);
+        const sph::State s1 = ws_state(ws, L.s1, prm, n);
+        const sph::State s2 = ws_state(ws, L.s2, prm, n);
+        SPH_TRY(copy(user, s2));
+        sph::State cur = s2, nxt = s1;
+        SPH_TRY(zero_counts());
+        for (int64_t s = 0; s < k; ++s) {
+            tape_records(s);
+            SPH_TRY(sort_into(cur, nxt, true, false));
+            SPH_TRY(density(nxt, start(), start() + 1, true));
+            SPH_TRY(momentum(nxt, start(), start() + 1, true));
+            std::swap(cur, nxt);
+        }
+        const int64_t N = n;
+        const double hdt = 0.5 * prm->dt;
+        double* bufs[2] = {(double*)(ws + L.lamB), (double*)(ws + L.lamC)};
+        const double* in = lam_in;
+        for (int64_t s = k - 1; s >= 0; --s) {
+            tape_records(s);
+            double* out = s == 0 ? lam_out : bufs[s & 1];
+            SPH_TRY(adjoint_rhs(in + DIM * N, in + 2 * DIM * N, N, hdt, typetape, nullptr, dJ));
+            Timed t_(K_ADJ_KICK, st);
+            sph::k_adj_kick<DIM><<<blocks_for(n), sph::kBlock, 0, st>>>(
+                n, in, (const double*)(ws + L.lxd), (const double*)(ws + L.lvd), typetape, perm(),
+                prm->dt, hdt, out);
+            SPH_TRY(launch_check("k_adj_kick"));
+            in = out;
+        }
+        default_records();
+        return SPH_OK;
+    }
+
+    // Adjoint of one acceleration evaluation at the (unsorted) state st.
+    int accel_backward(const sph_particles* stp, const double* lam_a, double* lam_x,
+                       double* lam_u, double* dJ) {
+        const sph::State user = user_state(stp);
+        const sph::State s1 = ws_state(ws, L.s1, prm, n);
+        default_records();
+        SPH_TRY(zero_counts());
+        SPH_TRY(sort_into(user, s1, false, false));
+        SPH_TRY(density(s1, start(), start() + 1, true));
+        SPH_TRY(adjoint_rhs(nullptr, lam_a, n, 0.0, s1.type, perm(), dJ));
+        Timed t_(K_ADJ_KICK, st);
+        sph::k_adj_accum<DIM><<<blocks_for(n), sph::kBlock, 0, st>>>(
+            n, (const double*)(ws + L.lxd), (const double*)(ws + L.lvd), s1.type, perm(), lam_x,
+            lam_u);
+        return launch_check("k_adj_accum");
+    }
 };
 
 template <template <int, int, typename> class F, typename... Args>
@@ -411,13 +673,13 @@ int dispatch(const sph_params* p, Args&&... args) {
 // Common preparation: grid, layout, workspace check, engine.
 template <int DIM, int KERNEL, typename T>
 int make_engine(const sph_params* p, const sph_particles* pa, void* ws, size_t ws_bytes,
-                void* stream, Engine<DIM, KERNEL, T>* E) {
+                void* stream, Engine<DIM, KERNEL, T>* E, int64_t adj_k = 0) {
     int64_t ncells;
     SPH_TRY(make_grid(p, &E->G, &ncells));
     E->prm = p;
     E->ncells = ncells;
     E->n = (int)pa->n;
-    E->L = make_layout(p, pa->n, ncells);
+    E->L = make_layout(p, pa->n, ncells, adj_k);
     if (!ws) return fail(SPH_EINVAL, "workspace is NULL");
     if ((uintptr_t)ws % 256 != 0) return fail(SPH_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < E->L.bytes)
@@ -425,6 +687,7 @@ int make_engine(const sph_params* p, const sph_particles* pa, void* ws, size_t w
     E->ws = (char*)ws;
     E->st = (hipStream_t)stream;
     E->C = pair_const<T>(p, E->G);
+    E->default_records();
     return SPH_OK;
 }
 
@@ -493,6 +756,26 @@ struct RunStep {
     }
 };
 
+template <int DIM, int KERNEL, typename T>
+struct RunStepBackward {
+    static int run(const sph_params* p, const sph_particles* ck, int64_t k, const double* lin,
+                   double* lout, double* dJ, void* ws, size_t wb, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        SPH_TRY(make_engine(p, ck, ws, wb, st, &E, k));
+        return E.step_backward(ck, k, lin, lout, dJ);
+    }
+};
+
+template <int DIM, int KERNEL, typename T>
+struct RunAccelBackward {
+    static int run(const sph_params* p, const sph_particles* stp, const double* la, double* lx,
+                   double* lu, double* dJ, void* ws, size_t wb, void* st) {
+        Engine<DIM, KERNEL, T> E;
+        SPH_TRY(make_engine(p, stp, ws, wb, st, &E, 1));
+        return E.accel_backward(stp, la, lx, lu, dJ);
+    }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -526,7 +809,7 @@ size_t sph_workspace_bytes(const sph_params* prm, int64_t n, int64_t adjoint_k) 
     sph::Grid G;
     int64_t ncells;
     if (make_grid(prm, &G, &ncells) != SPH_OK) return 0;
-    return make_layout(prm, n, ncells).bytes;
+    return make_layout(prm, n, ncells, adjoint_k).bytes;
 }
 
 int sph_bin_sort(const sph_params* prm, sph_particles* pa, void* ws, size_t ws_bytes,
@@ -591,18 +874,62 @@ int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t 
                       const double* lam_in, double* lam_out, double* dJ_dnu, void* ws,
                       size_t ws_bytes, void* stream) {
     g_err.clear();
-    (void)prm; (void)ckpt; (void)k; (void)lam_in; (void)lam_out; (void)dJ_dnu; (void)ws;
-    (void)ws_bytes; (void)stream;
-    return fail(SPH_EINVAL, "sph_step_backward: not available in this build");
+    SPH_TRY(check_params(prm, true));
+    SPH_TRY(check_particles(prm, ckpt));
+    if (k < 1) return fail(SPH_EINVAL, "k must be >= 1");
+    if (!lam_in || !lam_out || !dJ_dnu) return fail(SPH_EINVAL, "lam_in, lam_out or dJ_dnu is NULL");
+    if (lam_in == lam_out) return fail(SPH_EINVAL, "lam_in and lam_out may not alias");
+    return dispatch<RunStepBackward>(prm, ckpt, k, lam_in, lam_out, dJ_dnu, ws, ws_bytes, stream);
 }
 
 int sph_accel_backward(const sph_params* prm, const sph_particles* st, const double* lam_a,
                        double* lam_x, double* lam_u, double* dJ_dnu, void* ws, size_t ws_bytes,
                        void* stream) {
     g_err.clear();
-    (void)prm; (void)st; (void)lam_a; (void)lam_x; (void)lam_u; (void)dJ_dnu; (void)ws;
-    (void)ws_bytes; (void)stream;
-    return fail(SPH_EINVAL, "sph_accel_backward: not available in this build");
+    SPH_TRY(check_params(prm, false));
+    SPH_TRY(check_particles(prm, st));
+    if (!lam_a || !lam_x || !lam_u || !dJ_dnu)
+        return fail(SPH_EINVAL, "lam_a, lam_x, lam_u or dJ_dnu is NULL");
+    return dispatch<RunAccelBackward>(prm, st, lam_a, lam_x, lam_u, dJ_dnu, ws, ws_bytes, stream);
+}
+
+int sph_read_interactions(void* ws, size_t ws_bytes, int64_t* total, int reset, void* stream) {
+    g_err.clear();
+    if (!ws || ws_bytes < 256 || !total) return fail(SPH_EINVAL, "workspace or total is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long v = 0;
+    SPH_HIP(hipMemcpyAsync(&v, (char*)ws + 8, sizeof v, hipMemcpyDeviceToHost, st));
+    SPH_HIP(hipStreamSynchronize(st));
+    *total = (int64_t)v;
+    if (reset) {
+        SPH_HIP(hipMemsetAsync((char*)ws + 8, 0, sizeof v, st));
+        SPH_HIP(hipStreamSynchronize(st));
+    }
+    return SPH_OK;
+}
+
+int sph_timer_enable(int on) {
+    g_err.clear();
+    if (on != 0 && on != 1) return fail(SPH_EINVAL, "on must be 0 or 1");
+    g_timer.on = on != 0;
+    return SPH_OK;
+}
+
+int sph_timer_read(int nslots, const char** names, double* ms, int64_t* launches, int reset) {
+    g_err.clear();
+    g_timer.fold();
+    for (int k = 0; k < nslots && k < K_COUNT; ++k) {
+        if (names) names[k] = kKernelNames[k];
+        if (ms) ms[k] = g_timer.ms[k];
+        if (launches) launches[k] = g_timer.launches[k];
+    }
+    if (reset) {
+        for (int k = 0; k < K_COUNT; ++k) {
+            g_timer.ms[k] = 0.0;
+            g_timer.launches[k] = 0;
+        }
+    }
+    return K_COUNT;
 }
 
 int sph_check(void* ws, size_t ws_bytes, void* stream) {

@@ -81,6 +81,8 @@ struct PairConst {
     T g[3];        // body acceleration
     T cs[3];       // cell sizes
     T rho0, inv_rho0, B;  // Tait: p = B((rho/rho0)^7 - 1)
+    T sigma_h4;    // sigma / h^4 (adjoint only)
+    T b7;          // 7 B / rho0 = dp/drho at rho0 (adjoint only)
 };
 
 // ---------------------------------------------------------------------------
@@ -365,7 +367,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
                                                         uint32_t* __restrict__ skey,
                                                         typename Vec4<T>::type* __restrict__ pos,
                                                         typename Vec4<T>::type* __restrict__ vel,
-                                                        int copy_derived) {
+                                                        int copy_derived,
+                                                        uint8_t* __restrict__ type_tape) {
 #pragma clang fp contract(off)
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
@@ -392,7 +395,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
     }
     const double m = src.m[i];
     dst.m[d] = m;
-    dst.type[d] = src.type[i];
+    const uint8_t ty = src.type[i];
+    dst.type[d] = ty;
+    if (type_tape) type_tape[d] = ty;
     dst.id[d] = src.id[i];
     if (copy_derived) {
         ((T*)dst.rho)[d] = ((const T*)src.rho)[i];
@@ -443,26 +448,12 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
 }
 
 // ---------------------------------------------------------------------------
-// Summation density (eq. 2) and, if with_eos, the Tait EOS (eq. eos) with
-// P = p / rho^2 packed for the momentum pass.
-template <int DIM, int KERNEL, typename T>
-__global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
-                                                    const uint32_t* __restrict__ skey,
-                                                    const typename Vec4<T>::type* __restrict__ pos,
-                                                    const uint32_t* __restrict__ cstart,
-                                                    const uint32_t* __restrict__ cend,
-                                                    T* __restrict__ rho_out, T* __restrict__ p_out,
-                                                    typename Vec2<T>::type* __restrict__ rp,
-                                                    int with_eos) {
-    const int i = xcd_block() * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const typename Vec4<T>::type ri = pos[i];
-    T acc = T(0);
-    for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
-                              [&](uint32_t j, const typename Vec4<T>::type& rj, T, T, T, T r2) {
-                                  const T q = p_sqrt(r2) * C.inv_h;
-                                  acc += rj.w * kernel_w<KERNEL, T>(q, C.sigma);
-                              });
+// Density epilogue: store rho and, with_eos, p and (rho, P = p / rho^2).
+template <typename T>
+__device__ __forceinline__ void finish_density(int i, T acc, const PairConst<T>& C,
+                                               T* __restrict__ rho_out, T* __restrict__ p_out,
+                                               typename Vec2<T>::type* __restrict__ rp,
+                                               int with_eos) {
     rho_out[i] = acc;
     if (with_eos) {
         const T p = tait<T>(acc, C);
@@ -472,6 +463,40 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
         v2.y = p / (acc * acc);
         rp[i] = v2;
     }
+}
+
+// Summation density (eq. 2) and, if with_eos, the Tait EOS (eq. eos) with
+// P = p / rho^2 packed for the momentum pass.  Also adds the number of
+// interactions |N(i)| (self included) to *pairs, reduced per wave so that
+// one integer atomic per wave keeps the total exact and cheap.
+template <int DIM, int KERNEL, typename T>
+__global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
+                                                    const uint32_t* __restrict__ skey,
+                                                    const typename Vec4<T>::type* __restrict__ pos,
+                                                    const uint32_t* __restrict__ cstart,
+                                                    const uint32_t* __restrict__ cend,
+                                                    T* __restrict__ rho_out, T* __restrict__ p_out,
+                                                    typename Vec2<T>::type* __restrict__ rp,
+                                                    int with_eos,
+                                                    unsigned long long* __restrict__ pairs) {
+    const int i = xcd_block() * kBlock + threadIdx.x;
+    uint32_t cnt = 0;
+    if (i < n) {
+        const typename Vec4<T>::type ri = pos[i];
+        T acc = T(0);
+        for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend,
+                                  (uint32_t)n,
+                                  [&](uint32_t j, const typename Vec4<T>::type& rj, T, T, T,
+                                      T r2) {
+                                      const T q = p_sqrt(r2) * C.inv_h;
+                                      acc += rj.w * kernel_w<KERNEL, T>(q, C.sigma);
+                                      ++cnt;
+                                  });
+        finish_density<T>(i, acc, C, rho_out, p_out, rp, with_eos);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(pairs, (unsigned long long)cnt);
 }
 
 // Momentum equation for fluid particles (walls: a = 0):
