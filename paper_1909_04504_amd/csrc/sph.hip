@@ -333,6 +333,7 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
     for (int k = 0; k < 3; ++k) {
         C.g[k] = (T)p->g[k];
         C.cs[k] = (T)G.cs[k];
+        C.L[k] = (T)G.L[k];
     }
     C.rho0 = (T)p->rho0;
     C.inv_rho0 = (T)(1.0 / p->rho0);

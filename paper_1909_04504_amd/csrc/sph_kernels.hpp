@@ -81,6 +81,7 @@ struct PairConst {
     T g[3];        // body acceleration
     T cs[3];       // cell sizes
     T rho0, inv_rho0, B;  // Tait: p = B((rho/rho0)^7 - 1)
+    T L[3];        // box lengths (periodic image shifts)
     T sigma_h4;    // sigma / h^4 (adjoint only)
     T b7;          // 7 B / rho0 = dp/drho at rho0 (adjoint only)
 };
@@ -126,9 +127,18 @@ __device__ __forceinline__ T kernel_f(T q, T sigma_h2) {
 }
 
 // Tait EOS with the seventh power as r2 = r r, r4 = r2 r2, r7 = r4 r2 r.
+// FP64 divides by rho0 as the definition does: a rounded 1/rho0 would shift
+// r by an ulp, which (r^7 - 1) amplifies by about 1/(r - 1).
+__device__ __forceinline__ float density_ratio(float rho, const PairConst<float>& C) {
+    return rho * C.inv_rho0;
+}
+__device__ __forceinline__ double density_ratio(double rho, const PairConst<double>& C) {
+    return rho / C.rho0;
+}
+
 template <typename T>
 __device__ __forceinline__ T tait(T rho, const PairConst<T>& C) {
-    const T r = rho * C.inv_rho0;
+    const T r = density_ratio(rho, C);
     const T r2 = r * r;
     const T r4 = r2 * r2;
     return C.B * (r4 * r2 * r - T(1));
@@ -170,8 +180,46 @@ __device__ __forceinline__ int cell_coord(double x, const Grid& G, int k, bool* 
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour loop: calls f(j, dx, dy, dz, r2) for every sorted slot j with
-// |r_ij|^2 < R^2 in the (2S+1)^dim stencil cells of i's cell (self included).
+// Frame of the pair records.  Mixed precision stores float offsets from the
+// origin of the particle's own cell; FP64 stores absolute positions, so that
+// r_ij = fl(x_i - x_j), minus a periodic shift of +-L for wrapped stencil
+// cells, rounds exactly as the minimum-image difference of the definition.
+template <typename T> struct LocalFrame { static constexpr bool value = false; };
+template <> struct LocalFrame<float> { static constexpr bool value = true; };
+
+// Neighbour cell along one axis for stencil offset o, and the offset to
+// subtract from (d_i - d_j): o cs in the local frame (origin of j's cell
+// relative to i's), the periodic image shift in the global frame.  Returns
+// false if the cell is outside a non-periodic grid.
+template <typename T>
+__device__ __forceinline__ bool stencil_axis(int c, int o, int nc, int periodic, T cs, T L,
+                                             int* cell, T* off) {
+    int cc = c + o;
+    T shift = T(0);
+    if (cc < 0) {
+        if (!periodic) return false;
+        cc += nc;
+        shift = -L;
+    } else if (cc >= nc) {
+        if (!periodic) return false;
+        cc -= nc;
+        shift = L;
+    }
+    *cell = cc;
+    *off = LocalFrame<T>::value ? T(o) * cs : shift;
+    return true;
+}
+
+// Record coordinate of a particle at x in cell c along axis k.
+template <typename T>
+__device__ __forceinline__ T frame_coord(double x, int c, const Grid& G, int k) {
+    if (LocalFrame<T>::value) return (T)(x - (G.lo[k] + (double)c * G.cs[k]));
+    return (T)x;
+}
+
+// Neighbour loop: calls f(j, rec_j, dx, dy, dz, r2) for every sorted slot j
+// with |r_ij|^2 < R^2 in the (2S+1)^dim stencil cells of i's cell (self
+// included), r_ij = (d_i - d_j) - offset.
 template <int DIM, typename T, typename Fn>
 __device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst<T>& C,
                                                   uint32_t key, T dix, T diy, T diz,
@@ -185,32 +233,22 @@ __device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst
     const int zlo = DIM == 3 ? -S : 0, zhi = DIM == 3 ? S : 0;
     for (int oz = zlo; oz <= zhi; ++oz) {
         int cz = 0;
-        if (DIM == 3) {
-            cz = c[2] + oz;
-            if (G.periodic[2]) {
-                cz = cz < 0 ? cz + G.nc[2] : (cz >= G.nc[2] ? cz - G.nc[2] : cz);
-            } else if (cz < 0 || cz >= G.nc[2]) {
-                continue;
-            }
-        }
-        const T offz = T(oz) * C.cs[2];
+        T offz = T(0);
+        if (DIM == 3 && !stencil_axis<T>(c[2], oz, G.nc[2], G.periodic[2], C.cs[2], C.L[2], &cz,
+                                         &offz))
+            continue;
         for (int oy = -S; oy <= S; ++oy) {
-            int cy = c[1] + oy;
-            if (G.periodic[1]) {
-                cy = cy < 0 ? cy + G.nc[1] : (cy >= G.nc[1] ? cy - G.nc[1] : cy);
-            } else if (cy < 0 || cy >= G.nc[1]) {
+            int cy;
+            T offy;
+            if (!stencil_axis<T>(c[1], oy, G.nc[1], G.periodic[1], C.cs[1], C.L[1], &cy, &offy))
                 continue;
-            }
-            const T offy = T(oy) * C.cs[1];
             const uint32_t row = (uint32_t)G.nc[0] * ((uint32_t)cy + (uint32_t)G.nc[1] * (uint32_t)cz);
             for (int ox = -S; ox <= S; ++ox) {
-                int cx = c[0] + ox;
-                if (G.periodic[0]) {
-                    cx = cx < 0 ? cx + G.nc[0] : (cx >= G.nc[0] ? cx - G.nc[0] : cx);
-                } else if (cx < 0 || cx >= G.nc[0]) {
+                int cx;
+                T offx;
+                if (!stencil_axis<T>(c[0], ox, G.nc[0], G.periodic[0], C.cs[0], C.L[0], &cx,
+                                     &offx))
                     continue;
-                }
-                const T offx = T(ox) * C.cs[0];
                 const uint32_t cell = row + (uint32_t)cx;
                 const uint32_t b = cstart[cell];
                 uint32_t e = cend[cell];
@@ -390,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
         dst.x[q][d] = x;
         dst.u[q][d] = u;
         if (copy_derived) ((T*)dst.a[q])[d] = ((const T*)src.a[q])[i];
-        del[q] = (T)(x - (G.lo[q] + (double)c[q] * G.cs[q]));
+        del[q] = frame_coord<T>(x, c[q], G, q);
         vv[q] = (T)u;
     }
     const double m = src.m[i];
@@ -428,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
     for (int q = 0; q < DIM; ++q) {
         const double x = S.x[q][i];
         c[q] = cell_coord(x, G, q, &outside);
-        del[q] = (T)(x - (G.lo[q] + (double)c[q] * G.cs[q]));
+        del[q] = frame_coord<T>(x, c[q], G, q);
         vv[q] = (T)S.u[q][i];
     }
     skey[i] = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
