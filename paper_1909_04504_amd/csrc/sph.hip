@@ -325,6 +325,10 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
         sigma = p->dim == 2 ? 7.0 / (4.0 * pi * h * h) : 21.0 / (16.0 * pi * h * h * h);
     sph::PairConst<T> C;
     C.R2 = (T)(4.0 * h * h);
+    C.R2_d = 4.0 * h * h;
+    C.inv_h_d = 1.0 / h;
+    C.sigma_d = sigma;
+    for (int k = 0; k < 3; ++k) C.fix_scale[k] = G.cs[k] / (double)(1 << sph::kFixBits);
     C.inv_h = (T)(1.0 / h);
     C.sigma = (T)sigma;
     C.sigma_h2 = (T)(sigma / (h * h));
@@ -336,6 +340,8 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
         C.L[k] = (T)G.L[k];
     }
     C.rho0 = (T)p->rho0;
+    C.rho0_d = p->rho0;
+    C.B_d = p->rho0 * p->c0 * p->c0 / 7.0;
     C.inv_rho0 = (T)(1.0 / p->rho0);
     C.B = (T)(p->rho0 * p->c0 * p->c0 / 7.0);
     C.sigma_h4 = (T)(sigma / (h * h * h * h));
@@ -350,6 +356,7 @@ template <int DIM, int KERNEL, typename T>
 struct Engine {
     using V4 = typename sph::Vec4<T>::type;
     using V2 = typename sph::Vec2<T>::type;
+    using R4 = typename sph::Rec<T>::type;
     const sph_params* prm;
     sph::Grid G;
     int64_t ncells;
@@ -369,7 +376,7 @@ struct Engine {
 
     // Pair records and sort results of the current evaluation: the default
     // buffers, or one slot of the adjoint's recompute tape.
-    V4* posp = nullptr;
+    R4* posp = nullptr;
     V4* velp = nullptr;
     V2* rpp = nullptr;
     uint32_t* skeyp = nullptr;
@@ -379,12 +386,12 @@ struct Engine {
     uint32_t* perm() const { return permp; }
     uint32_t* skey() const { return skeyp; }
     uint32_t* start() const { return startp; }
-    V4* pos() const { return posp; }
+    R4* pos() const { return posp; }
     V4* vel() const { return velp; }
     V2* rp() const { return rpp; }
 
     void default_records() {
-        posp = (V4*)(ws + L.pos);
+        posp = (R4*)(ws + L.pos);
         velp = (V4*)(ws + L.vel);
         rpp = (V2*)(ws + L.rp);
         skeyp = (uint32_t*)(ws + L.skey);
@@ -394,7 +401,7 @@ struct Engine {
     }
     void tape_records(int64_t slot) {
         char* b = ws + L.tape + (size_t)slot * L.slot_bytes;
-        posp = (V4*)(b + L.slot.pos);
+        posp = (R4*)(b + L.slot.pos);
         velp = (V4*)(b + L.slot.vel);
         rpp = (V2*)(b + L.slot.rp);
         skeyp = (uint32_t*)(b + L.slot.skey);
@@ -425,14 +432,17 @@ struct Engine {
 
     // hash (with the opening half kick + drift if drift), counting sort, and
     // gather of src into dst in sorted order with pair records packed.
-    int sort_into(const sph::State& src, const sph::State& dst, bool drift, bool copy_derived) {
+    // hashed: src already holds the drifted positions with keys and counts
+    // (from the epilogue of the previous momentum launch).
+    int sort_into(const sph::State& src, const sph::State& dst, bool drift, bool copy_derived,
+                  bool hashed = false) {
         const unsigned nb = blocks_for(n);
         using TA = T;
-        {
-        Timed t_(K_HASH, st);
-        sph::k_drift_hash<DIM, TA><<<nb, sph::kBlock, 0, st>>>(n, src, G, 0.5 * prm->dt, prm->dt,
-                                                              drift ? 1 : 0, key(), counts(), flags());
-        SPH_TRY(launch_check("k_drift_hash"));
+        if (!hashed) {
+            Timed t_(K_HASH, st);
+            sph::k_drift_hash<DIM, TA><<<nb, sph::kBlock, 0, st>>>(
+                n, src, G, 0.5 * prm->dt, prm->dt, drift ? 1 : 0, key(), counts(), flags());
+            SPH_TRY(launch_check("k_drift_hash"));
         }
         SPH_TRY(scan<uint32_t>(counts(), ncells, start()));
         {
@@ -454,11 +464,23 @@ struct Engine {
         return launch_check("k_density");
     }
 
-    int momentum(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool kick) {
-        Timed t_(K_MOMENTUM, st);
-        sph::k_momentum<DIM, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
-            n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, s, kick ? 1 : 0, 0.5 * prm->dt);
-        return launch_check("k_momentum");
+    // kick: close the step; drift: open the next one (hash + count);
+    // diag_out: KE and momentum after the kick, 1 + DIM doubles.
+    int momentum(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool kick,
+                 bool drift = false, double* diag_out = nullptr) {
+        double* part = diag_out ? (double*)(ws + L.diag) : nullptr;
+        const unsigned nb = blocks_for(n);
+        {
+            Timed t_(K_MOMENTUM, st);
+            sph::k_momentum<DIM, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, s, kick ? 1 : 0,
+                drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(), flags(), part);
+            SPH_TRY(launch_check("k_momentum"));
+        }
+        if (!diag_out) return SPH_OK;
+        Timed t_(K_DIAG, st);
+        sph::k_diag_final<DIM><<<1, sph::kBlock, 0, st>>>((int)nb, part, diag_out);
+        return launch_check("k_diag_final");
     }
 
     int pack(const sph::State& s, bool with_rp) {
@@ -472,19 +494,6 @@ struct Engine {
         Timed t_(K_COPY, st);
         sph::k_copy_state<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, src, dst);
         return launch_check("k_copy_state");
-    }
-
-    int diag(const sph::State& s, double* out) {
-        const unsigned nb = blocks_for(n);
-        double* part = (double*)(ws + L.diag);
-        {
-        Timed t_(K_DIAG, st);
-        sph::k_diag_partial<DIM><<<nb, sph::kBlock, 0, st>>>(n, s, part);
-        SPH_TRY(launch_check("k_diag_partial"));
-        }
-        Timed t_(K_DIAG, st);
-        sph::k_diag_final<DIM><<<1, sph::kBlock, 0, st>>>((int)nb, part, out);
-        return launch_check("k_diag_final");
     }
 
     // --- entry points ---------------------------------------------------
@@ -550,18 +559,21 @@ struct Engine {
         const uint32_t* cs = start();
         const uint32_t* ce = start() + 1;
         SPH_TRY(zero_counts());
+        bool hashed = false;  // cur already drifted and hashed by a fused epilogue
         if (prime) {
             SPH_TRY(sort_into(cur, nxt, false, false));
             SPH_TRY(density(nxt, cs, ce, true));
-            SPH_TRY(momentum(nxt, cs, ce, false));
+            SPH_TRY(momentum(nxt, cs, ce, false, nsteps > 0));
             std::swap(cur, nxt);
+            hashed = nsteps > 0;
         }
         for (int64_t s = 0; s < nsteps; ++s) {
-            SPH_TRY(sort_into(cur, nxt, true, false));
+            const bool last = s == nsteps - 1;
+            SPH_TRY(sort_into(cur, nxt, true, false, hashed));
             SPH_TRY(density(nxt, cs, ce, true));
-            SPH_TRY(momentum(nxt, cs, ce, true));
-            if (diag_out) SPH_TRY(diag(nxt, diag_out + s * (1 + DIM)));
+            SPH_TRY(momentum(nxt, cs, ce, true, !last, diag_out ? diag_out + s * (1 + DIM) : nullptr));
             std::swap(cur, nxt);
+            hashed = !last;
         }
         if (cur.m != user.m) SPH_TRY(copy(cur, user));
         return SPH_OK;
@@ -616,9 +628,9 @@ struct Engine {
         SPH_TRY(zero_counts());
         for (int64_t s = 0; s < k; ++s) {
             tape_records(s);
-            SPH_TRY(sort_into(cur, nxt, true, false));
+            SPH_TRY(sort_into(cur, nxt, true, false, s > 0));
             SPH_TRY(density(nxt, start(), start() + 1, true));
-            SPH_TRY(momentum(nxt, start(), start() + 1, true));
+            SPH_TRY(momentum(nxt, start(), start() + 1, true, s < k - 1));
             std::swap(cur, nxt);
         }
         const int64_t N = n;

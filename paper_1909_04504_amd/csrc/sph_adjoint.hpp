@@ -79,22 +79,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(int n, const double* __rest
 template <int DIM, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_pair1(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
-    const typename Vec4<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
+    const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
     const typename Vec2<T>::type* __restrict__ rp, const typename Vec4<T>::type* __restrict__ lhat,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
     double* __restrict__ lx, double* __restrict__ lv, T* __restrict__ lrho,
     double* __restrict__ nupart) {
     const int i = xcd_block() * kBlock + threadIdx.x;
     if (i >= n) return;
-    const typename Vec4<T>::type ri = pos[i];
+    const typename Rec<T>::type ri = pos[i];
     const typename Vec4<T>::type vi = vel[i];
     const typename Vec2<T>::type rpi = rp[i];
     const typename Vec4<T>::type li = lhat[i];
     const T h = p_rcp(C.inv_h);
+    const T mi = rec_mass(ri);
     T gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0, lP = 0, lR = 0, nu_acc = 0;
     for_each_neighbor<DIM, T>(
-        G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
-        [&](uint32_t j, const typename Vec4<T>::type& rj, T dx, T dy, T dz, T r2) {
+        G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+        [&](uint32_t j, const typename Rec<T>::type& rj, const Geom<T>& g) {
+            const T r2 = g.r2;
+            const T dx = g.d[0], dy = g.d[1], dz = g.d[2];
             if (j == (uint32_t)i || r2 == T(0)) return;
             const typename Vec4<T>::type vj = vel[j];
             const typename Vec2<T>::type rpj = rp[j];
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
             const T G1 = F1 * r2 * inv_den + T(2) * F * C.eta_h2 * inv_den * inv_den;
             const T inv_rs = p_rcp(rpi.x + rpj.x);
             const T c4 = C.four_nu * inv_rs;
-            const T mj = rj.w, mi = ri.w;
+            const T mj = rec_mass(rj);
             const T wx = mj * li.x - mi * lj.x;
             const T wy = mj * li.y - mi * lj.y;
             const T wz = DIM == 3 ? mj * li.z - mi * lj.z : T(0);
@@ -155,24 +158,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
 template <int DIM, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_pair2(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
-    const typename Vec4<T>::type* __restrict__ pos, const T* __restrict__ lrho,
+    const typename Rec<T>::type* __restrict__ pos, const T* __restrict__ lrho,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
     double* __restrict__ lx) {
     const int i = xcd_block() * kBlock + threadIdx.x;
     if (i >= n) return;
-    const typename Vec4<T>::type ri = pos[i];
+    const typename Rec<T>::type ri = pos[i];
     const T lri = lrho[i];
+    const T mi = rec_mass(ri);
     T ax = 0, ay = 0, az = 0;
     for_each_neighbor<DIM, T>(
-        G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
-        [&](uint32_t j, const typename Vec4<T>::type& rj, T dx, T dy, T dz, T r2) {
-            if (j == (uint32_t)i || r2 == T(0)) return;
-            const T q = p_sqrt(r2) * C.inv_h;
+        G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+        [&](uint32_t j, const typename Rec<T>::type& rj, const Geom<T>& g) {
+            if (j == (uint32_t)i || g.r2 == T(0)) return;
+            const T q = p_sqrt(g.r2) * C.inv_h;
             const T F = kernel_f<KERNEL, T>(q, C.sigma_h2);
-            const T c = (lri * rj.w + lrho[j] * ri.w) * F;
-            ax += c * dx;
-            ay += c * dy;
-            if (DIM == 3) az += c * dz;
+            const T c = (lri * rec_mass(rj) + lrho[j] * mi) * F;
+            ax += c * g.d[0];
+            ay += c * g.d[1];
+            if (DIM == 3) az += c * g.d[2];
         });
     lx[i] += (double)ax;
     lx[(int64_t)n + i] += (double)ay;

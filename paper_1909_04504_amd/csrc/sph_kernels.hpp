@@ -65,6 +65,28 @@ struct State {
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
+
+// Position record of a sorted particle: FP64 keeps the absolute position and
+// the mass; mixed precision keeps fixed-point offsets from the centre of the
+// particle's cell (2^27 units per cell, int32) and the mass as float bits.
+template <typename T> struct Rec;
+template <> struct Rec<double> { using type = double4; };
+template <> struct Rec<float> { using type = int4; };
+constexpr int kFixBits = 27;
+constexpr int kFixClamp = (1 << 29) - 1;  // offsets within 4 cells of the centre
+
+__device__ __forceinline__ double rec_mass(const double4& r) { return r.w; }
+__device__ __forceinline__ float rec_mass(const int4& r) { return __int_as_float(r.w); }
+
+// Separation of a candidate pair: r_ij in the pair precision, |r_ij|^2 in the
+// pair precision and in FP64 (the neighbour predicate and the density terms
+// use the FP64 value).
+template <typename T>
+struct Geom {
+    T d[3];
+    T r2;
+    double r2d;
+};
 template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
@@ -81,7 +103,11 @@ struct PairConst {
     T g[3];        // body acceleration
     T cs[3];       // cell sizes
     T rho0, inv_rho0, B;  // Tait: p = B((rho/rho0)^7 - 1)
+    double rho0_d, B_d;   // the same in FP64 (per-particle EOS)
     T L[3];        // box lengths (periodic image shifts)
+    double R2_d;         // (2h)^2 in FP64: the neighbour predicate
+    double inv_h_d, sigma_d;  // FP64 density terms
+    double fix_scale[3];      // cell size / 2^27: one fixed-point unit
     T sigma_h4;    // sigma / h^4 (adjoint only)
     T b7;          // 7 B / rho0 = dp/drho at rho0 (adjoint only)
 };
@@ -126,22 +152,17 @@ __device__ __forceinline__ T kernel_f(T q, T sigma_h2) {
     }
 }
 
-// Tait EOS with the seventh power as r2 = r r, r4 = r2 r2, r7 = r4 r2 r.
-// FP64 divides by rho0 as the definition does: a rounded 1/rho0 would shift
-// r by an ulp, which (r^7 - 1) amplifies by about 1/(r - 1).
-__device__ __forceinline__ float density_ratio(float rho, const PairConst<float>& C) {
-    return rho * C.inv_rho0;
-}
-__device__ __forceinline__ double density_ratio(double rho, const PairConst<double>& C) {
-    return rho / C.rho0;
-}
-
+// Tait EOS, evaluated per particle in FP64 in both precisions, with the
+// seventh power as r2 = r r, r4 = r2 r2, r7 = r4 r2 r.  In mixed precision
+// the pair terms are FP32 but the density sum and this per-particle
+// evaluation are FP64: the EOS multiplies density rounding by about
+// 7 B / rho0 before it reaches the pressure force.
 template <typename T>
-__device__ __forceinline__ T tait(T rho, const PairConst<T>& C) {
-    const T r = density_ratio(rho, C);
-    const T r2 = r * r;
-    const T r4 = r2 * r2;
-    return C.B * (r4 * r2 * r - T(1));
+__device__ __forceinline__ double tait64(double rho, const PairConst<T>& C) {
+    const double r = rho / C.rho0_d;
+    const double r2 = r * r;
+    const double r4 = r2 * r2;
+    return C.B_d * (r4 * r2 * r - 1.0);
 }
 
 // Map the hardware workgroup id to a logical block so that each XCD (blocks
@@ -180,50 +201,92 @@ __device__ __forceinline__ int cell_coord(double x, const Grid& G, int k, bool* 
 }
 
 // ---------------------------------------------------------------------------
-// Frame of the pair records.  Mixed precision stores float offsets from the
-// origin of the particle's own cell; FP64 stores absolute positions, so that
-// r_ij = fl(x_i - x_j), minus a periodic shift of +-L for wrapped stencil
-// cells, rounds exactly as the minimum-image difference of the definition.
-template <typename T> struct LocalFrame { static constexpr bool value = false; };
-template <> struct LocalFrame<float> { static constexpr bool value = true; };
+// Frames of the pair records.
+//  * FP64: absolute positions; r_ij = fl(x_i - x_j) minus a periodic shift of
+//    +-L for a wrapped stencil cell, which rounds exactly as the minimum-image
+//    difference of the definition.
+//  * Mixed precision: fixed-point offsets k from the centre of the particle's
+//    cell; r_ij = (k_i - k_j - o 2^27) units, an exact integer (o the stencil
+//    offset of j's cell), converted once.  Positions are quantised to
+//    cs/2^27 (~4e-11 for the workloads here), far below float resolution.
+// Both are exactly antisymmetric (r_ji = -r_ij bitwise), so the neighbour
+// predicate |r|^2 < (2h)^2, evaluated in FP64, is symmetric.
 
-// Neighbour cell along one axis for stencil offset o, and the offset to
-// subtract from (d_i - d_j): o cs in the local frame (origin of j's cell
-// relative to i's), the periodic image shift in the global frame.  Returns
-// false if the cell is outside a non-periodic grid.
-template <typename T>
-__device__ __forceinline__ bool stencil_axis(int c, int o, int nc, int periodic, T cs, T L,
-                                             int* cell, T* off) {
+// Neighbour cell along one axis for stencil offset o; returns false outside a
+// non-periodic grid.  wrap = -1 / +1 if the periodic stencil wrapped.
+__device__ __forceinline__ bool stencil_axis(int c, int o, int nc, int periodic, int* cell,
+                                             int* wrap) {
     int cc = c + o;
-    T shift = T(0);
+    *wrap = 0;
     if (cc < 0) {
         if (!periodic) return false;
         cc += nc;
-        shift = -L;
+        *wrap = -1;
     } else if (cc >= nc) {
         if (!periodic) return false;
         cc -= nc;
-        shift = L;
+        *wrap = 1;
     }
     *cell = cc;
-    *off = LocalFrame<T>::value ? T(o) * cs : shift;
     return true;
 }
 
-// Record coordinate of a particle at x in cell c along axis k.
-template <typename T>
-__device__ __forceinline__ T frame_coord(double x, int c, const Grid& G, int k) {
-    if (LocalFrame<T>::value) return (T)(x - (G.lo[k] + (double)c * G.cs[k]));
-    return (T)x;
+// Record coordinates of a particle at x in cell c along axis k.
+__device__ __forceinline__ double frame_coord64(double x) { return x; }
+__device__ __forceinline__ int frame_coord_fix(double x, int c, const Grid& G, int k) {
+    const double centre = G.lo[k] + ((double)c + 0.5) * G.cs[k];
+    double u = rint((x - centre) / G.cs[k] * (double)(1 << kFixBits));
+    if (!(u == u)) u = 0.0;  // non-finite positions are flagged by the hash
+    u = u > (double)kFixClamp ? (double)kFixClamp : (u < -(double)kFixClamp ? -(double)kFixClamp : u);
+    return (int)u;
 }
 
-// Neighbour loop: calls f(j, rec_j, dx, dy, dz, r2) for every sorted slot j
-// with |r_ij|^2 < R^2 in the (2S+1)^dim stencil cells of i's cell (self
-// included), r_ij = (d_i - d_j) - offset.
+template <typename T>
+__device__ __forceinline__ typename Rec<T>::type make_rec(const double* x, const int* c, double m,
+                                                          const Grid& G, int dim);
+template <>
+__device__ __forceinline__ double4 make_rec<double>(const double* x, const int*, double m,
+                                                    const Grid&, int dim) {
+    double4 r;
+    r.x = x[0];
+    r.y = x[1];
+    r.z = dim == 3 ? x[2] : 0.0;
+    r.w = m;
+    return r;
+}
+template <>
+__device__ __forceinline__ int4 make_rec<float>(const double* x, const int* c, double m,
+                                                const Grid& G, int dim) {
+    int4 r;
+    r.x = frame_coord_fix(x[0], c[0], G, 0);
+    r.y = frame_coord_fix(x[1], c[1], G, 1);
+    r.z = dim == 3 ? frame_coord_fix(x[2], c[2], G, 2) : 0;
+    r.w = __float_as_int((float)m);
+    return r;
+}
+
+// Per-axis separation of record rj from ri for the stencil offset o / wrap.
+__device__ __forceinline__ double sep_axis(const double4& ri, const double4& rj, int k, int o,
+                                           int wrap, const PairConst<double>& C) {
+    const double di = k == 0 ? ri.x : (k == 1 ? ri.y : ri.z);
+    const double dj = k == 0 ? rj.x : (k == 1 ? rj.y : rj.z);
+    (void)o;
+    return (di - dj) - (wrap == 0 ? 0.0 : (wrap < 0 ? -C.L[k] : C.L[k]));
+}
+__device__ __forceinline__ double sep_axis(const int4& ri, const int4& rj, int k, int o, int,
+                                           const PairConst<float>& C) {
+    const int di = k == 0 ? ri.x : (k == 1 ? ri.y : ri.z);
+    const int dj = k == 0 ? rj.x : (k == 1 ? rj.y : rj.z);
+    return (double)((di - dj) - o * (1 << kFixBits)) * C.fix_scale[k];
+}
+
+// Neighbour loop: calls f(j, rec_j, geom) for every sorted slot j with
+// |r_ij|^2 < (2h)^2 in the (2S+1)^dim stencil cells of i's cell (self
+// included).
 template <int DIM, typename T, typename Fn>
 __device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst<T>& C,
-                                                  uint32_t key, T dix, T diy, T diz,
-                                                  const typename Vec4<T>::type* __restrict__ pos,
+                                                  uint32_t key, const typename Rec<T>::type& ri,
+                                                  const typename Rec<T>::type* __restrict__ pos,
                                                   const uint32_t* __restrict__ cstart,
                                                   const uint32_t* __restrict__ cend, uint32_t n,
                                                   Fn&& f) {
@@ -232,38 +295,38 @@ __device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst
     const int S = G.S;
     const int zlo = DIM == 3 ? -S : 0, zhi = DIM == 3 ? S : 0;
     for (int oz = zlo; oz <= zhi; ++oz) {
-        int cz = 0;
-        T offz = T(0);
-        if (DIM == 3 && !stencil_axis<T>(c[2], oz, G.nc[2], G.periodic[2], C.cs[2], C.L[2], &cz,
-                                         &offz))
-            continue;
+        int cz = 0, wz = 0;
+        if (DIM == 3 && !stencil_axis(c[2], oz, G.nc[2], G.periodic[2], &cz, &wz)) continue;
         for (int oy = -S; oy <= S; ++oy) {
-            int cy;
-            T offy;
-            if (!stencil_axis<T>(c[1], oy, G.nc[1], G.periodic[1], C.cs[1], C.L[1], &cy, &offy))
-                continue;
+            int cy, wy;
+            if (!stencil_axis(c[1], oy, G.nc[1], G.periodic[1], &cy, &wy)) continue;
             const uint32_t row = (uint32_t)G.nc[0] * ((uint32_t)cy + (uint32_t)G.nc[1] * (uint32_t)cz);
             for (int ox = -S; ox <= S; ++ox) {
-                int cx;
-                T offx;
-                if (!stencil_axis<T>(c[0], ox, G.nc[0], G.periodic[0], C.cs[0], C.L[0], &cx,
-                                     &offx))
-                    continue;
+                int cx, wx;
+                if (!stencil_axis(c[0], ox, G.nc[0], G.periodic[0], &cx, &wx)) continue;
                 const uint32_t cell = row + (uint32_t)cx;
                 const uint32_t b = cstart[cell];
                 uint32_t e = cend[cell];
                 e = e < n ? e : n;
                 for (uint32_t j = b; j < e; ++j) {
-                    const typename Vec4<T>::type rj = pos[j];
-                    const T dx = (dix - rj.x) - offx;
-                    const T dy = (diy - rj.y) - offy;
-                    T r2 = dx * dx + dy * dy;
-                    T dz = T(0);
+                    const typename Rec<T>::type rj = pos[j];
+                    const double dx = sep_axis(ri, rj, 0, ox, wx, C);
+                    const double dy = sep_axis(ri, rj, 1, oy, wy, C);
+                    double r2 = dx * dx + dy * dy;
+                    double dz = 0.0;
                     if (DIM == 3) {
-                        dz = (diz - rj.z) - offz;
+                        dz = sep_axis(ri, rj, 2, oz, wz, C);
                         r2 += dz * dz;
                     }
-                    if (r2 < C.R2) f(j, rj, dx, dy, dz, r2);
+                    if (r2 < C.R2_d) {
+                        Geom<T> g;
+                        g.d[0] = (T)dx;
+                        g.d[1] = (T)dy;
+                        g.d[2] = (T)dz;
+                        g.r2 = (T)r2;
+                        g.r2d = r2;
+                        f(j, rj, g);
+                    }
                 }
             }
         }
@@ -271,28 +334,25 @@ __device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst
 }
 
 // ---------------------------------------------------------------------------
-// Hash (and optionally the opening half kick + drift + periodic wrap):
-//   v = u + dt/2 a;  x <- wrap(x + dt v)   (fluid only; walls have v = 0)
-// then key = cell of x, counts[key] += 1.
-template <int DIM, typename TA>
-__global__ __launch_bounds__(kBlock) void k_drift_hash(int n, State S, Grid G, double hdt,
-                                                       double dt, int drift,
-                                                       uint32_t* __restrict__ key,
-                                                       uint32_t* __restrict__ counts,
-                                                       uint32_t* __restrict__ flags) {
+// Opening half kick + drift + periodic wrap of one particle (fluid only;
+// walls keep x and get v = 0), then its cell key and one count for the sort:
+//   v = u + dt/2 a;  x <- wrap(x + dt v);  key = cell(x);  counts[key] += 1.
+// With drift = false only the key and count of the current x.
+template <int DIM>
+__device__ __forceinline__ void drift_and_hash(int i, const State& S, const Grid& G, bool fluid,
+                                               const double* u, const double* a, double hdt,
+                                               double dt, bool drift, uint32_t* __restrict__ key,
+                                               uint32_t* __restrict__ counts,
+                                               uint32_t* __restrict__ flags) {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
     bool outside = false, nonfinite = false;
     int c[3] = {0, 0, 0};
-    const bool fluid = S.type[i] == 0;
     for (int k = 0; k < DIM; ++k) {
         double x = S.x[k][i];
         if (drift) {
             double v = 0.0;
             if (fluid) {
-                const double a = (double)((const TA*)S.a[k])[i];
-                v = S.u[k][i] + hdt * a;
+                v = u[k] + hdt * a[k];
                 x = x + dt * v;
                 if (G.periodic[k]) {
                     const double hi = G.lo[k] + G.L[k];
@@ -313,6 +373,41 @@ __global__ __launch_bounds__(kBlock) void k_drift_hash(int n, State S, Grid G, d
     atomicAdd(&counts[kk], 1u);
     if (outside) atomicOr(flags, kFlagOutside);
     if (nonfinite) atomicOr(flags, kFlagNonFinite);
+}
+
+// Standalone hash (first step of a call, or a plain sort).
+template <int DIM, typename TA>
+__global__ __launch_bounds__(kBlock) void k_drift_hash(int n, State S, Grid G, double hdt,
+                                                       double dt, int drift,
+                                                       uint32_t* __restrict__ key,
+                                                       uint32_t* __restrict__ counts,
+                                                       uint32_t* __restrict__ flags) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
+    if (drift)
+        for (int k = 0; k < DIM; ++k) {
+            u[k] = S.u[k][i];
+            a[k] = (double)((const TA*)S.a[k])[i];
+        }
+    drift_and_hash<DIM>(i, S, G, S.type[i] == 0, u, a, hdt, dt, drift != 0, key, counts, flags);
+}
+
+// Block sum of up to four FP64 values per thread into part[q * nparts + b]
+// (fixed tree order).
+template <int NV>
+__device__ __forceinline__ void block_sum4(const double* v, double* __restrict__ part, int b,
+                                           int nparts) {
+    __shared__ double sh[NV][kBlock];
+    for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NV; ++q) part[(int64_t)q * nparts + b] = sh[q][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -403,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
                                                         State src, State dst, Grid G,
                                                         uint32_t* __restrict__ perm,
                                                         uint32_t* __restrict__ skey,
-                                                        typename Vec4<T>::type* __restrict__ pos,
+                                                        typename Rec<T>::type* __restrict__ pos,
                                                         typename Vec4<T>::type* __restrict__ vel,
                                                         int copy_derived,
                                                         uint8_t* __restrict__ type_tape) {
@@ -420,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
     skey[d] = k;
     int c[3];
     decode_key(k, G, c);
-    T del[3] = {T(0), T(0), T(0)};
+    double xs[3] = {0.0, 0.0, 0.0};
     T vv[3] = {T(0), T(0), T(0)};
     for (int q = 0; q < DIM; ++q) {
         const double x = src.x[q][i];
@@ -428,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
         dst.x[q][d] = x;
         dst.u[q][d] = u;
         if (copy_derived) ((T*)dst.a[q])[d] = ((const T*)src.a[q])[i];
-        del[q] = frame_coord<T>(x, c[q], G, q);
+        xs[q] = x;
         vv[q] = (T)u;
     }
     const double m = src.m[i];
@@ -441,10 +536,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
         ((T*)dst.rho)[d] = ((const T*)src.rho)[i];
         ((T*)dst.p)[d] = ((const T*)src.p)[i];
     }
-    typename Vec4<T>::type pr, vr;
-    pr.x = del[0]; pr.y = del[1]; pr.z = del[2]; pr.w = (T)m;
+    typename Vec4<T>::type vr;
     vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
-    pos[d] = pr;
+    pos[d] = make_rec<T>(xs, c, m, G, DIM);
     vel[d] = vr;
 }
 
@@ -453,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
                                                  uint32_t* __restrict__ skey,
-                                                 typename Vec4<T>::type* __restrict__ pos,
+                                                 typename Rec<T>::type* __restrict__ pos,
                                                  typename Vec4<T>::type* __restrict__ vel,
                                                  typename Vec2<T>::type* __restrict__ rp,
                                                  int with_rp) {
@@ -461,19 +555,18 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
     if (i >= n) return;
     bool outside = false;
     int c[3] = {0, 0, 0};
-    T del[3] = {T(0), T(0), T(0)};
+    double xs[3] = {0.0, 0.0, 0.0};
     T vv[3] = {T(0), T(0), T(0)};
     for (int q = 0; q < DIM; ++q) {
         const double x = S.x[q][i];
         c[q] = cell_coord(x, G, q, &outside);
-        del[q] = frame_coord<T>(x, c[q], G, q);
+        xs[q] = x;
         vv[q] = (T)S.u[q][i];
     }
     skey[i] = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
-    typename Vec4<T>::type pr, vr;
-    pr.x = del[0]; pr.y = del[1]; pr.z = del[2]; pr.w = (T)S.m[i];
+    typename Vec4<T>::type vr;
     vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
-    pos[i] = pr;
+    pos[i] = make_rec<T>(xs, c, S.m[i], G, DIM);
     vel[i] = vr;
     if (with_rp) {
         const T rho = ((const T*)S.rho)[i];
@@ -486,19 +579,20 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
 }
 
 // ---------------------------------------------------------------------------
-// Density epilogue: store rho and, with_eos, p and (rho, P = p / rho^2).
+// Density epilogue: store rho and, with_eos, p and (rho, P = p / rho^2),
+// computed in FP64 and rounded to the pair type.
 template <typename T>
-__device__ __forceinline__ void finish_density(int i, T acc, const PairConst<T>& C,
+__device__ __forceinline__ void finish_density(int i, double rho, const PairConst<T>& C,
                                                T* __restrict__ rho_out, T* __restrict__ p_out,
                                                typename Vec2<T>::type* __restrict__ rp,
                                                int with_eos) {
-    rho_out[i] = acc;
+    rho_out[i] = (T)rho;
     if (with_eos) {
-        const T p = tait<T>(acc, C);
-        p_out[i] = p;
+        const double p = tait64<T>(rho, C);
+        p_out[i] = (T)p;
         typename Vec2<T>::type v2;
-        v2.x = acc;
-        v2.y = p / (acc * acc);
+        v2.x = (T)rho;
+        v2.y = (T)(p / (rho * rho));
         rp[i] = v2;
     }
 }
@@ -510,7 +604,7 @@ __device__ __forceinline__ void finish_density(int i, T acc, const PairConst<T>&
 template <int DIM, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
                                                     const uint32_t* __restrict__ skey,
-                                                    const typename Vec4<T>::type* __restrict__ pos,
+                                                    const typename Rec<T>::type* __restrict__ pos,
                                                     const uint32_t* __restrict__ cstart,
                                                     const uint32_t* __restrict__ cend,
                                                     T* __restrict__ rho_out, T* __restrict__ p_out,
@@ -520,14 +614,16 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
     const int i = xcd_block() * kBlock + threadIdx.x;
     uint32_t cnt = 0;
     if (i < n) {
-        const typename Vec4<T>::type ri = pos[i];
-        T acc = T(0);
-        for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend,
-                                  (uint32_t)n,
-                                  [&](uint32_t j, const typename Vec4<T>::type& rj, T, T, T,
-                                      T r2) {
-                                      const T q = p_sqrt(r2) * C.inv_h;
-                                      acc += rj.w * kernel_w<KERNEL, T>(q, C.sigma);
+        const typename Rec<T>::type ri = pos[i];
+        // The density terms are FP64 in both precisions: the EOS multiplies
+        // density rounding by ~7 B / rho0 before it reaches the forces.
+        double acc = 0.0;
+        for_each_neighbor<DIM, T>(G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+                                  [&](uint32_t j, const typename Rec<T>::type& rj,
+                                      const Geom<T>& g) {
+                                      const double q = sqrt(g.r2d) * C.inv_h_d;
+                                      acc += (double)rec_mass(rj) *
+                                             kernel_w<KERNEL, double>(q, C.sigma_d);
                                       ++cnt;
                                   });
         finish_density<T>(i, acc, C, rho_out, p_out, rp, with_eos);
@@ -540,95 +636,111 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
 // Momentum equation for fluid particles (walls: a = 0):
 //   a_i = g + sum_{j != i} m_j [ -(P_i + P_j) F r_ij
 //                               + 4 nu/(rho_i+rho_j) F |r|^2/(|r|^2 + eta h^2) v_ij ]
-// with F = (dW/dr)/r.  kick = 1 also closes the step: u = v + dt/2 a (FP64).
+// with F = (dW/dr)/r.  Epilogue (FP64, per particle, in registers):
+//   kick  = 1: close the step, u = v + dt/2 a (walls: u = 0);
+//   diag != 0: per-block partial sums of m|u|^2/2 and m u into diag_part;
+//   drift = 1: open the next step (half kick, drift, wrap, hash and count),
+//              leaving v of the next step in u.
 template <int DIM, int KERNEL, typename T>
-__global__ __launch_bounds__(kBlock) void k_momentum(int n, Grid G, PairConst<T> C,
-                                                     const uint32_t* __restrict__ skey,
-                                                     const typename Vec4<T>::type* __restrict__ pos,
-                                                     const typename Vec4<T>::type* __restrict__ vel,
-                                                     const typename Vec2<T>::type* __restrict__ rp,
-                                                     const uint8_t* __restrict__ type,
-                                                     const uint32_t* __restrict__ cstart,
-                                                     const uint32_t* __restrict__ cend, State S,
-                                                     int kick, double hdt) {
-    const int i = xcd_block() * kBlock + threadIdx.x;
-    if (i >= n) return;
-    T* a0 = (T*)S.a[0];
-    T* a1 = (T*)S.a[1];
-    T* a2 = (T*)S.a[2];
-    if (type[i] != 0) {
-        a0[i] = T(0);
-        a1[i] = T(0);
-        if (DIM == 3) a2[i] = T(0);
-        if (kick) {
-            S.u[0][i] = 0.0;
-            S.u[1][i] = 0.0;
-            if (DIM == 3) S.u[2][i] = 0.0;
+__global__ __launch_bounds__(kBlock) void k_momentum(
+    int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
+    const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
+    const typename Vec2<T>::type* __restrict__ rp, const uint8_t* __restrict__ type,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, State S, int kick,
+    int drift, double hdt, double dt, uint32_t* __restrict__ key, uint32_t* __restrict__ counts,
+    uint32_t* __restrict__ flags, double* __restrict__ diag_part) {
+    const int blk = xcd_block();
+    const int i = blk * kBlock + threadIdx.x;
+    double dv[1 + DIM];
+    for (int q = 0; q <= DIM; ++q) dv[q] = 0.0;
+    if (i < n) {
+        const bool fluid = type[i] == 0;
+        T acc[3] = {T(0), T(0), T(0)};
+        if (fluid) {
+            const typename Rec<T>::type ri = pos[i];
+            const typename Vec4<T>::type vi = vel[i];
+            const typename Vec2<T>::type rpi = rp[i];
+            T ax = C.g[0], ay = C.g[1], az = C.g[2];
+            for_each_neighbor<DIM, T>(
+                G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+                [&](uint32_t j, const typename Rec<T>::type& rj, const Geom<T>& g) {
+                    if (j == (uint32_t)i) return;
+                    const typename Vec4<T>::type vj = vel[j];
+                    const typename Vec2<T>::type rpj = rp[j];
+                    const T r2 = g.r2;
+                    const T q = p_sqrt(r2) * C.inv_h;
+                    const T F = kernel_f<KERNEL, T>(q, C.sigma_h2);
+                    const T pres = -(rpi.y + rpj.y) * F;
+                    const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
+                    const T mj = rec_mass(rj);
+                    ax += mj * (pres * g.d[0] + visc * (vi.x - vj.x));
+                    ay += mj * (pres * g.d[1] + visc * (vi.y - vj.y));
+                    if (DIM == 3) az += mj * (pres * g.d[2] + visc * (vi.z - vj.z));
+                });
+            acc[0] = ax;
+            acc[1] = ay;
+            acc[2] = az;
         }
-        return;
-    }
-    const typename Vec4<T>::type ri = pos[i];
-    const typename Vec4<T>::type vi = vel[i];
-    const typename Vec2<T>::type rpi = rp[i];
-    T ax = C.g[0], ay = C.g[1], az = C.g[2];
-    for_each_neighbor<DIM, T>(
-        G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
-        [&](uint32_t j, const typename Vec4<T>::type& rj, T dx, T dy, T dz, T r2) {
-            if (j == (uint32_t)i) return;
-            const typename Vec4<T>::type vj = vel[j];
-            const typename Vec2<T>::type rpj = rp[j];
-            const T q = p_sqrt(r2) * C.inv_h;
-            const T F = kernel_f<KERNEL, T>(q, C.sigma_h2);
-            const T pres = -(rpi.y + rpj.y) * F;
-            const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
-            const T mj = rj.w;
-            ax += mj * (pres * dx + visc * (vi.x - vj.x));
-            ay += mj * (pres * dy + visc * (vi.y - vj.y));
-            if (DIM == 3) az += mj * (pres * dz + visc * (vi.z - vj.z));
-        });
-    a0[i] = ax;
-    a1[i] = ay;
-    if (DIM == 3) a2[i] = az;
-    if (kick) {
+        for (int k = 0; k < DIM; ++k) ((T*)S.a[k])[i] = acc[k];
+        double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
+        {
 #pragma clang fp contract(off)
-        S.u[0][i] = S.u[0][i] + hdt * (double)ax;
-        S.u[1][i] = S.u[1][i] + hdt * (double)ay;
-        if (DIM == 3) S.u[2][i] = S.u[2][i] + hdt * (double)az;
+            for (int k = 0; k < DIM; ++k) {
+                a[k] = (double)acc[k];
+                const double uk = S.u[k][i];
+                u[k] = kick ? (fluid ? uk + hdt * a[k] : 0.0) : uk;
+            }
+            if (diag_part) {
+                const double m = S.m[i];
+                double u2 = 0.0;
+                for (int k = 0; k < DIM; ++k) {
+                    u2 += u[k] * u[k];
+                    dv[1 + k] = m * u[k];
+                }
+                dv[0] = 0.5 * m * u2;
+            }
+        }
+        if (drift) {
+            drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags);
+        } else if (kick) {
+            for (int k = 0; k < DIM; ++k) S.u[k][i] = u[k];
+        }
     }
+    if (diag_part) block_sum4<1 + DIM>(dv, diag_part, blk, gridDim.x);
 }
 
 // Neighbour counts (phase 1) and lists (phase 2) of sph_neighbors.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_count(int n, Grid G, PairConst<T> C,
                                                       const uint32_t* __restrict__ skey,
-                                                      const typename Vec4<T>::type* __restrict__ pos,
+                                                      const typename Rec<T>::type* __restrict__ pos,
                                                       const uint32_t* __restrict__ cstart,
                                                       const uint32_t* __restrict__ cend,
                                                       uint32_t* __restrict__ cnt) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const typename Vec4<T>::type ri = pos[i];
+    const typename Rec<T>::type ri = pos[i];
     uint32_t c = 0;
-    for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
-                              [&](uint32_t, const typename Vec4<T>::type&, T, T, T, T) { ++c; });
+    for_each_neighbor<DIM, T>(G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+                              [&](uint32_t, const typename Rec<T>::type&, const Geom<T>&) { ++c; });
     cnt[i] = c;
 }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_fill(int n, Grid G, PairConst<T> C,
                                                      const uint32_t* __restrict__ skey,
-                                                     const typename Vec4<T>::type* __restrict__ pos,
+                                                     const typename Rec<T>::type* __restrict__ pos,
                                                      const uint32_t* __restrict__ cstart,
                                                      const uint32_t* __restrict__ cend,
                                                      const int64_t* __restrict__ off,
                                                      int32_t* __restrict__ nbr) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const typename Vec4<T>::type ri = pos[i];
+    const typename Rec<T>::type ri = pos[i];
     int64_t w = off[i];
     const int64_t wend = off[i + 1];
-    for_each_neighbor<DIM, T>(G, C, skey[i], ri.x, ri.y, ri.z, pos, cstart, cend, (uint32_t)n,
-                              [&](uint32_t j, const typename Vec4<T>::type&, T, T, T, T) {
+    for_each_neighbor<DIM, T>(G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+                              [&](uint32_t j, const typename Rec<T>::type&, const Geom<T>&) {
                                   if (w < wend) nbr[w++] = (int32_t)j;
                               });
 }
@@ -639,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void k_eos(int n, PairConst<T> C, const T* 
                                                 T* __restrict__ p) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    p[i] = tait<T>(rho[i], C);
+    p[i] = (T)tait64<T>((double)rho[i], C);
 }
 
 // Fill with a constant (used instead of a memset so the sequence can be
@@ -680,34 +792,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_state(int n, State src, State d
 
 // ---------------------------------------------------------------------------
 // FP64 diagnostics: KE = sum m |u|^2 / 2 and momentum sum m u, as fixed-order
-// tree sums (per-block partials, then one block over the partials).
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_diag_partial(int n, State S,
-                                                         double* __restrict__ part) {
-    __shared__ double sh[4][kBlock];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < n) {
-        const double m = S.m[i];
-        double u2 = 0.0;
-        for (int q = 0; q < DIM; ++q) {
-            const double u = S.u[q][i];
-            u2 += u * u;
-            v[1 + q] = m * u;
-        }
-        v[0] = 0.5 * m * u2;
-    }
-    for (int q = 0; q < 1 + DIM; ++q) sh[q][threadIdx.x] = v[q];
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int q = 0; q < 1 + DIM; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 1 + DIM; ++q) part[(int64_t)q * gridDim.x + blockIdx.x] = sh[q][0];
-}
-
+// tree sums: per-block partials (momentum epilogue), then one block over them.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_diag_final(int nparts, const double* __restrict__ part,
                                                        double* __restrict__ out) {

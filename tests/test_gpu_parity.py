@@ -145,11 +145,17 @@ def test_step_prime_evaluation(case, prec):
 
 
 def test_taylor_green_64_trajectory_fp64():
-    """50 FP64 predictor-corrector steps of the 64x64 Taylor-Green vortex:
-    every field within 1e-12 of the oracle, matched by id."""
+    """50 FP64 predictor-corrector steps of the 64x64 Taylor-Green vortex,
+    matched by id: positions, velocities, density, pressure and diagnostics
+    within 1e-12 of the oracle.  The acceleration is ill-conditioned in the
+    positions (a one-ulp change of x moves it by ~1e-12 relative), so its
+    bar is the oracle's own spread under a one-ulp perturbation of x0, and
+    never looser than 1e-11."""
     wl = W.workload("tg64")
     p, s = wl.params, wl.state
     ref = oracle.step(p, s.x, s.u, s.m, s.ptype, wl.steps, want_diag=True)
+    ref_ulp = oracle.step(p, np.nextafter(s.x, 2.0), s.u, s.m, s.ptype, wl.steps)
+    spread = normwise(ref_ulp["a"], ref["a"])
     prm = sph.make_params(p, sph.FP64)
     dp = sph.DeviceParticles.from_state(s, sph.FP64)
     ws = sph.workspace(prm, s.n)
@@ -160,10 +166,14 @@ def test_taylor_green_64_trajectory_fp64():
     dx = out["x"][:, o] - ref["x"]
     dx -= np.round(dx)
     assert np.abs(dx).max() < 1e-12
-    for f in ("u", "a"):
-        assert normwise(out[f][:, o], ref[f]) < 1e-12, f
-    for f in ("rho", "p"):
-        assert np.abs(out[f][o] - ref[f]).max() < 1e-12 * max(1.0, np.abs(ref[f]).max()), f
+    assert normwise(out["u"][:, o], ref["u"]) < 1e-12
+    err_a = normwise(out["a"][:, o], ref["a"])
+    assert err_a < max(1e-12, min(1e-11, 4 * spread)), (err_a, spread)
+    assert normwise(out["rho"][o], ref["rho"]) < 1e-12
+    # pressure against its scale B = rho0 c0^2 / 7 (the EOS amplifies density
+    # rounding by 7 B / rho0)
+    B = p.rho0 * p.c0 ** 2 / 7
+    assert np.abs(out["p"][o] - ref["p"]).max() / B < 1e-12
     d = diag.cpu().numpy()
     assert np.abs(d[:, 0] / ref["diag"][:, 0] - 1).max() < 1e-12
     assert np.abs(d[:, 1:] - ref["diag"][:, 1:]).max() < 1e-12 * 0.25
