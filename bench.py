@@ -169,6 +169,35 @@ def roofline(res, wl, prec, steps):
     return out
 
 
+def adjoint_ratio(sph, torch, steps=200, k=20, reps=2):
+    """Backward (recompute + adjoint kernels) time over forward (with the
+    checkpoint copies) time of the differentiable rollout on the 256x256
+    Taylor-Green workload, mixed precision."""
+    import sph_workloads as W
+    from paper_1909_04504_amd.autograd import rollout_ke
+    wl = W.workload("tg256")
+    p, s = wl.params, wl.state
+    best = None
+    for _ in range(reps + 1):
+        u0 = torch.tensor(s.u, dtype=torch.float64, device="cuda", requires_grad=True)
+        nu = torch.tensor(p.nu, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ke = rollout_ke(u0, nu, p, s.x, s.m, s.ptype, steps, k, sph.FP32_MIXED)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ke.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        cur = (t1 - t0, t2 - t1)
+        if best is None or sum(cur) < sum(best):
+            best = cur
+    fwd, bwd = best
+    return {"workload": f"{wl.name}: {s.n} particles, {steps} steps, checkpoint every {k}",
+            "forward_ms": 1e3 * fwd, "backward_ms": 1e3 * bwd, "ratio": bwd / fwd,
+            "forward_ms_per_step": 1e3 * fwd / steps}
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 CPU oracle, single-threaded, on a bounded sample of the same
     workload: the first steps from the same initial state."""
@@ -211,6 +240,7 @@ def main():
     ap.add_argument("--workload", default="tg512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (8 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run")
@@ -245,6 +275,10 @@ def main():
         fp64 = run_precision(sph, torch, wl, sph.FP64, args.steps, args.warmup, True)
         print(f"# fp64: {fp64['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     rl = roofline(mixed, wl, sph.FP32_MIXED, args.steps)
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_ratio(sph, torch)
+        print(f"# adjoint/forward: {adj['ratio']:.2f}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl)
@@ -270,7 +304,8 @@ def main():
         "fp32_mixed": mixed,
         "fp64": fp64,
         "fp64_vs_mixed_time": (fp64["ms_per_step"] / mixed["ms_per_step"]) if fp64 else None,
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": adj["ratio"] if adj else None,
+        "adjoint": adj,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
         "source_digest": source_digest(),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "sph.h"
@@ -238,7 +239,9 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
     };
     const int64_t longest = (ncells + 1 > n + 1) ? ncells + 1 : n + 1;
     const size_t nchunks = (size_t)((longest + sph::kScanChunk - 1) / sph::kScanChunk);
-    L.flags = take(256);
+    // header (flag word at 0, number of interaction counters at 8), then one
+    // 64-bit interaction counter per density block from offset 16
+    L.flags = take(16 + 8 * (size_t)blocks_for(n));
     L.counts = take(4 * (size_t)ncells);
     L.start = take(4 * ((size_t)ncells + 1));
     L.chunks = take(8 * nchunks);
@@ -367,7 +370,7 @@ struct Engine {
     sph::PairConst<T> C;
 
     uint32_t* flags() const { return (uint32_t*)(ws + L.flags); }
-    unsigned long long* pairs() const { return (unsigned long long*)(ws + L.flags + 8); }
+    unsigned long long* pairs() const { return (unsigned long long*)(ws + L.flags + 16); }
     uint32_t* counts() const { return (uint32_t*)(ws + L.counts); }
     uint64_t* chunks() const { return (uint64_t*)(ws + L.chunks); }
     uint32_t* key() const { return (uint32_t*)(ws + L.key); }
@@ -408,6 +411,15 @@ struct Engine {
         permp = (uint32_t*)(b + L.slot.perm);
         typetape = (uint8_t*)(b + L.slot.type);
         startp = (uint32_t*)(b + L.slot.start);
+    }
+
+    // Calls fn(std::integral_constant<int, S>) for the grid's stencil reach.
+    template <typename Fn>
+    void with_reach(Fn&& fn) const {
+        if (G.S == 2)
+            fn(std::integral_constant<int, 2>());
+        else
+            fn(std::integral_constant<int, 1>());
     }
 
     int zero_counts() {
@@ -459,8 +471,10 @@ struct Engine {
 
     int density(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_eos) {
         Timed t_(K_DENSITY, st);
-        sph::k_density<DIM, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
-            n, G, C, skey(), pos(), cs, ce, (T*)s.rho, (T*)s.p, rp(), with_eos ? 1 : 0, pairs());
+        with_reach([&](auto R) {
+            sph::k_density<DIM, decltype(R)::value, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+                n, G, C, skey(), pos(), cs, ce, (T*)s.rho, (T*)s.p, rp(), with_eos ? 1 : 0, pairs());
+        });
         return launch_check("k_density");
     }
 
@@ -472,9 +486,11 @@ struct Engine {
         const unsigned nb = blocks_for(n);
         {
             Timed t_(K_MOMENTUM, st);
-            sph::k_momentum<DIM, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
-                n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, s, kick ? 1 : 0,
-                drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(), flags(), part);
+            with_reach([&](auto R) {
+                sph::k_momentum<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                    n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, s, kick ? 1 : 0,
+                    drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(), flags(), part);
+            });
             SPH_TRY(launch_check("k_momentum"));
         }
         if (!diag_out) return SPH_OK;
@@ -533,8 +549,10 @@ struct Engine {
         SPH_TRY(pack(user, false));
         {
         Timed t_(K_NBR_COUNT, st);
-        sph::k_nbr_count<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, G, C, skey(), pos(), cs,
-                                                                       ce, ncnt());
+        with_reach([&](auto R) {
+            sph::k_nbr_count<DIM, decltype(R)::value, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+                n, G, C, skey(), pos(), cs, ce, ncnt());
+        });
         SPH_TRY(launch_check("k_nbr_count"));
         }
         SPH_TRY(scan<int64_t>(ncnt(), n, offsets));
@@ -547,8 +565,10 @@ struct Engine {
                         (long long)tot, (long long)capacity);
         if (tot > 0 && !nbr) return fail(SPH_EINVAL, "nbr is NULL");
         Timed t_(K_NBR_FILL, st);
-        sph::k_nbr_fill<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, G, C, skey(), pos(), cs,
-                                                                      ce, offsets, nbr);
+        with_reach([&](auto R) {
+            sph::k_nbr_fill<DIM, decltype(R)::value, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+                n, G, C, skey(), pos(), cs, ce, offsets, nbr);
+        });
         return launch_check("k_nbr_fill");
     }
 
@@ -599,15 +619,19 @@ struct Engine {
         }
         {
             Timed t_(K_ADJ_PAIR1, st);
-            sph::k_adj_pair1<DIM, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
-                n, G, C, skey(), pos(), vel(), rp(), lhat, start(), start() + 1, lxd, lvd, lrho,
-                nup);
+            with_reach([&](auto R) {
+                sph::k_adj_pair1<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                    n, G, C, skey(), pos(), vel(), rp(), lhat, start(), start() + 1, lxd, lvd,
+                    lrho, nup);
+            });
             SPH_TRY(launch_check("k_adj_pair1"));
         }
         {
             Timed t_(K_ADJ_PAIR2, st);
-            sph::k_adj_pair2<DIM, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
-                n, G, C, skey(), pos(), lrho, start(), start() + 1, lxd);
+            with_reach([&](auto R) {
+                sph::k_adj_pair2<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                    n, G, C, skey(), pos(), lrho, start(), start() + 1, lxd);
+            });
             SPH_TRY(launch_check("k_adj_pair2"));
         }
         Timed t_(K_ADJ_REDUCE, st);
@@ -910,12 +934,20 @@ int sph_read_interactions(void* ws, size_t ws_bytes, int64_t* total, int reset, 
     g_err.clear();
     if (!ws || ws_bytes < 256 || !total) return fail(SPH_EINVAL, "workspace or total is NULL");
     hipStream_t st = (hipStream_t)stream;
-    unsigned long long v = 0;
-    SPH_HIP(hipMemcpyAsync(&v, (char*)ws + 8, sizeof v, hipMemcpyDeviceToHost, st));
+    unsigned long long nb = 0;
+    SPH_HIP(hipMemcpyAsync(&nb, (char*)ws + 8, sizeof nb, hipMemcpyDeviceToHost, st));
     SPH_HIP(hipStreamSynchronize(st));
-    *total = (int64_t)v;
+    *total = 0;
+    if (nb == 0) return SPH_OK;  // no density evaluation yet
+    if (16 + 8 * nb > ws_bytes) return fail(SPH_EINVAL, "corrupt interaction counter header");
+    std::vector<unsigned long long> v(nb);
+    SPH_HIP(hipMemcpyAsync(v.data(), (char*)ws + 16, 8 * nb, hipMemcpyDeviceToHost, st));
+    SPH_HIP(hipStreamSynchronize(st));
+    unsigned long long t = 0;
+    for (unsigned long long x : v) t += x;
+    *total = (int64_t)t;
     if (reset) {
-        SPH_HIP(hipMemsetAsync((char*)ws + 8, 0, sizeof v, st));
+        SPH_HIP(hipMemsetAsync((char*)ws + 16, 0, 8 * nb, st));
         SPH_HIP(hipStreamSynchronize(st));
     }
     return SPH_OK;

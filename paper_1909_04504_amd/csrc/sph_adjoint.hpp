@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(int n, const double* __rest
 }
 
 // First gather: direct position and velocity adjoints, lam_rho, nu partials.
-template <int DIM, int KERNEL, typename T>
+template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_pair1(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
     const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
@@ -93,15 +93,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
     const T h = p_rcp(C.inv_h);
     const T mi = rec_mass(ri);
     T gx = 0, gy = 0, gz = 0, hx = 0, hy = 0, hz = 0, lP = 0, lR = 0, nu_acc = 0;
-    for_each_neighbor<DIM, T>(
-        G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
-        [&](uint32_t j, const typename Rec<T>::type& rj, const Geom<T>& g) {
+    struct Pay {
+        typename Vec4<T>::type v;
+        typename Vec2<T>::type rp;
+        typename Vec4<T>::type l;
+    };
+    for_each_neighbor_p<DIM, SR, T>(
+        G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
+        [&](uint32_t j) { return Pay{vel[j], rp[j], lhat[j]}; },
+        [&](uint32_t j, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
             const T r2 = g.r2;
             const T dx = g.d[0], dy = g.d[1], dz = g.d[2];
             if (j == (uint32_t)i || r2 == T(0)) return;
-            const typename Vec4<T>::type vj = vel[j];
-            const typename Vec2<T>::type rpj = rp[j];
-            const typename Vec4<T>::type lj = lhat[j];
+            const typename Vec4<T>::type vj = pj.v;
+            const typename Vec2<T>::type rpj = pj.rp;
+            const typename Vec4<T>::type lj = pj.l;
             const T r = p_sqrt(r2);
             const T inv_r = p_rcp(r);
             const T q = r * C.inv_h;
@@ -155,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
 }
 
 // Second gather: lam_x_i += sum_j (lam_rho_i m_j + lam_rho_j m_i) F r_ij.
-template <int DIM, int KERNEL, typename T>
+template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_pair2(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
     const typename Rec<T>::type* __restrict__ pos, const T* __restrict__ lrho,
@@ -167,13 +173,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair2(
     const T lri = lrho[i];
     const T mi = rec_mass(ri);
     T ax = 0, ay = 0, az = 0;
-    for_each_neighbor<DIM, T>(
-        G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
-        [&](uint32_t j, const typename Rec<T>::type& rj, const Geom<T>& g) {
+    for_each_neighbor_p<DIM, SR, T>(
+        G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n, [&](uint32_t j) { return lrho[j]; },
+        [&](uint32_t j, const typename Rec<T>::type& rj, const T& lrj, const Geom<T>& g) {
             if (j == (uint32_t)i || g.r2 == T(0)) return;
             const T q = p_sqrt(g.r2) * C.inv_h;
             const T F = kernel_f<KERNEL, T>(q, C.sigma_h2);
-            const T c = (lri * rec_mass(rj) + lrho[j] * mi) * F;
+            const T c = (lri * rec_mass(rj) + lrj * mi) * F;
             ax += c * g.d[0];
             ay += c * g.d[1];
             if (DIM == 3) az += c * g.d[2];

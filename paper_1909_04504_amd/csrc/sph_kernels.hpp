@@ -280,56 +280,188 @@ __device__ __forceinline__ double sep_axis(const int4& ri, const int4& rj, int k
     return (double)((di - dj) - o * (1 << kFixBits)) * C.fix_scale[k];
 }
 
-// Neighbour loop: calls f(j, rec_j, geom) for every sorted slot j with
-// |r_ij|^2 < (2h)^2 in the (2S+1)^dim stencil cells of i's cell (self
-// included).
-template <int DIM, typename T, typename Fn>
-__device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst<T>& C,
-                                                  uint32_t key, const typename Rec<T>::type& ri,
-                                                  const typename Rec<T>::type* __restrict__ pos,
-                                                  const uint32_t* __restrict__ cstart,
-                                                  const uint32_t* __restrict__ cend, uint32_t n,
-                                                  Fn&& f) {
+// Test of one candidate j at x stencil offset ox: calls f if |r_ij| < 2h.
+template <int DIM, typename T, typename P, typename Fn>
+__device__ __forceinline__ void visit_candidate(uint32_t j, const typename Rec<T>::type& rj,
+                                                const P& pay, const typename Rec<T>::type& ri,
+                                                int ox, int wx, int oy, int wy, int oz, int wz,
+                                                const PairConst<T>& C, Fn& f) {
+    const double dx = sep_axis(ri, rj, 0, ox, wx, C);
+    const double dy = sep_axis(ri, rj, 1, oy, wy, C);
+    double r2 = dx * dx + dy * dy;
+    double dz = 0.0;
+    if (DIM == 3) {
+        dz = sep_axis(ri, rj, 2, oz, wz, C);
+        r2 += dz * dz;
+    }
+    if (r2 < C.R2_d) {
+        Geom<T> g;
+        g.d[0] = (T)dx;
+        g.d[1] = (T)dy;
+        g.d[2] = (T)dz;
+        g.r2 = (T)r2;
+        g.r2d = r2;
+        f(j, rj, pay, g);
+    }
+}
+
+// No per-candidate payload beyond the position record.
+struct NoPayload {
+    __device__ __forceinline__ int operator()(uint32_t) const { return 0; }
+};
+
+// The slot ranges of one stencil row: the cells cx-S .. cx+S of row `row`,
+// split where a periodic x boundary wraps; piece k covers cells
+// [first[k], last[k]] with periodic image wrap[k].  Pieces that do not exist
+// are empty (first > last).
+template <int S>
+__device__ __forceinline__ void row_pieces(int cx, const Grid& G, int first[2], int last[2],
+                                           int wrap[2]) {
+    const int nc = G.nc[0];
+    const int lo = cx - S, hi = cx + S;
+    first[1] = 1;
+    last[1] = 0;
+    wrap[1] = 0;
+    wrap[0] = 0;
+    if (!G.periodic[0]) {
+        first[0] = lo < 0 ? 0 : lo;
+        last[0] = hi > nc - 1 ? nc - 1 : hi;
+    } else if (lo < 0) {
+        first[0] = lo + nc;
+        last[0] = nc - 1;
+        wrap[0] = -1;
+        first[1] = 0;
+        last[1] = hi;
+    } else if (hi > nc - 1) {
+        first[0] = lo;
+        last[0] = nc - 1;
+        first[1] = 0;
+        last[1] = hi - nc;
+        wrap[1] = 1;
+    } else {
+        first[0] = lo;
+        last[0] = hi;
+    }
+}
+
+// Neighbour loop: calls f(j, rec_j, payload_j, geom) for every sorted slot j
+// with |r_ij|^2 < (2h)^2 in the (2S+1)^dim stencil cells of i's cell (self
+// included), payload_j = load(j).
+//  * The cells of one stencil row are adjacent in memory (row-major keys), so
+//    a row is walked as one slot range (two if it wraps a periodic x
+//    boundary).  A candidate's x offset comes from its own sorted key:
+//    ox = (cx_j - cx_i) + wrap nc.
+//  * The ranges of all rows of a stencil plane are loaded before any
+//    candidate; candidates are taken four at a time with their records and
+//    payloads loaded ahead of the arithmetic, so each lane keeps several
+//    independent loads in flight instead of one dependent chain.
+template <int DIM, int S, typename T, typename Load, typename Fn>
+__device__ __forceinline__ void for_each_neighbor_p(const Grid& G, const PairConst<T>& C,
+                                                    uint32_t key,
+                                                    const typename Rec<T>::type& ri,
+                                                    const typename Rec<T>::type* __restrict__ pos,
+                                                    const uint32_t* __restrict__ skey,
+                                                    const uint32_t* __restrict__ cstart,
+                                                    const uint32_t* __restrict__ cend,
+                                                    uint32_t n, Load&& load, Fn&& f) {
+    using R = typename Rec<T>::type;
+    constexpr int NR = 2 * S + 1;
     int c[3];
     decode_key(key, G, c);
-    const int S = G.S;
-    const int zlo = DIM == 3 ? -S : 0, zhi = DIM == 3 ? S : 0;
-    for (int oz = zlo; oz <= zhi; ++oz) {
+    int first[2], last[2], wrap[2];
+    row_pieces<S>(c[0], G, first, last, wrap);
+#pragma unroll
+    for (int zi = 0; zi < (DIM == 3 ? NR : 1); ++zi) {
+        const int oz = DIM == 3 ? zi - S : 0;
         int cz = 0, wz = 0;
         if (DIM == 3 && !stencil_axis(c[2], oz, G.nc[2], G.periodic[2], &cz, &wz)) continue;
-        for (int oy = -S; oy <= S; ++oy) {
+        // phase A: slot ranges of the rows of this plane
+        uint32_t pb[NR][2], pe[NR][2], prow[NR];
+        int pwy[NR];
+#pragma unroll
+        for (int yi = 0; yi < NR; ++yi) {
             int cy, wy;
-            if (!stencil_axis(c[1], oy, G.nc[1], G.periodic[1], &cy, &wy)) continue;
+            const bool ok = stencil_axis(c[1], yi - S, G.nc[1], G.periodic[1], &cy, &wy);
             const uint32_t row = (uint32_t)G.nc[0] * ((uint32_t)cy + (uint32_t)G.nc[1] * (uint32_t)cz);
-            for (int ox = -S; ox <= S; ++ox) {
-                int cx, wx;
-                if (!stencil_axis(c[0], ox, G.nc[0], G.periodic[0], &cx, &wx)) continue;
-                const uint32_t cell = row + (uint32_t)cx;
-                const uint32_t b = cstart[cell];
-                uint32_t e = cend[cell];
-                e = e < n ? e : n;
-                for (uint32_t j = b; j < e; ++j) {
-                    const typename Rec<T>::type rj = pos[j];
-                    const double dx = sep_axis(ri, rj, 0, ox, wx, C);
-                    const double dy = sep_axis(ri, rj, 1, oy, wy, C);
-                    double r2 = dx * dx + dy * dy;
-                    double dz = 0.0;
-                    if (DIM == 3) {
-                        dz = sep_axis(ri, rj, 2, oz, wz, C);
-                        r2 += dz * dz;
-                    }
-                    if (r2 < C.R2_d) {
-                        Geom<T> g;
-                        g.d[0] = (T)dx;
-                        g.d[1] = (T)dy;
-                        g.d[2] = (T)dz;
-                        g.r2 = (T)r2;
-                        g.r2d = r2;
-                        f(j, rj, g);
-                    }
+            prow[yi] = row;
+            pwy[yi] = wy;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                uint32_t b = 0, e = 0;
+                if (ok && first[k] <= last[k]) {
+                    b = cstart[row + (uint32_t)first[k]];
+                    e = cend[row + (uint32_t)last[k]];
+                    e = e < n ? e : n;
+                }
+                pb[yi][k] = b;
+                pe[yi][k] = e;
+            }
+        }
+        // phase B: the candidates, four at a time
+#pragma unroll
+        for (int yi = 0; yi < NR; ++yi) {
+            const int oy = yi - S, wy = pwy[yi];
+            const int xbase = (int)prow[yi] + c[0];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int wx = wrap[k];
+                const int xoff = wx * G.nc[0] - xbase;
+                auto ox_of = [&](uint32_t j) { return (int)skey[j] + xoff; };
+                const uint32_t e = pe[yi][k];
+                uint32_t j = pb[yi][k];
+                for (; j + 4 <= e; j += 4) {
+                    const R r0 = pos[j], r1 = pos[j + 1], r2 = pos[j + 2], r3 = pos[j + 3];
+                    const int o0 = ox_of(j), o1 = ox_of(j + 1), o2 = ox_of(j + 2), o3 = ox_of(j + 3);
+                    const auto p0 = load(j), p1 = load(j + 1), p2 = load(j + 2), p3 = load(j + 3);
+                    visit_candidate<DIM, T>(j, r0, p0, ri, o0, wx, oy, wy, oz, wz, C, f);
+                    visit_candidate<DIM, T>(j + 1, r1, p1, ri, o1, wx, oy, wy, oz, wz, C, f);
+                    visit_candidate<DIM, T>(j + 2, r2, p2, ri, o2, wx, oy, wy, oz, wz, C, f);
+                    visit_candidate<DIM, T>(j + 3, r3, p3, ri, o3, wx, oy, wy, oz, wz, C, f);
+                }
+                for (; j < e; ++j) {
+                    const R rj = pos[j];
+                    const int oj = ox_of(j);
+                    const auto pj = load(j);
+                    visit_candidate<DIM, T>(j, rj, pj, ri, oj, wx, oy, wy, oz, wz, C, f);
                 }
             }
         }
+    }
+}
+
+// Neighbour loop without payload: f(j, rec_j, geom).
+template <int DIM, int S, typename T, typename Fn>
+__device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst<T>& C,
+                                                  uint32_t key, const typename Rec<T>::type& ri,
+                                                  const typename Rec<T>::type* __restrict__ pos,
+                                                  const uint32_t* __restrict__ skey,
+                                                  const uint32_t* __restrict__ cstart,
+                                                  const uint32_t* __restrict__ cend, uint32_t n,
+                                                  Fn&& f) {
+    for_each_neighbor_p<DIM, S, T>(G, C, key, ri, pos, skey, cstart, cend, n, NoPayload(),
+                                   [&](uint32_t j, const typename Rec<T>::type& rj, int,
+                                       const Geom<T>& g) { f(j, rj, g); });
+}
+
+// ---------------------------------------------------------------------------
+// Lanes of the wave holding the same key (active lanes only): the group's
+// leader lane, this lane's rank in the group (lane order) and the group size.
+// The particles of a wave are consecutive in the previous sorted order, so a
+// wave holds ~dim-dependent few distinct cells and the loop runs once per
+// distinct key; one atomic per group replaces one per particle.
+__device__ __forceinline__ void wave_group(uint32_t key, int* leader, int* rank, int* size) {
+    const int lane = __lane_id();
+    unsigned long long rem = __ballot(1);
+    while (rem) {
+        const int l = __ffsll((long long)rem) - 1;
+        const uint32_t lk = __builtin_amdgcn_readlane(key, l);
+        const unsigned long long m = __ballot(key == lk);
+        if (key == lk) {
+            *leader = l;
+            *rank = __popcll(m & ((1ull << lane) - 1ull));
+            *size = __popcll(m);
+        }
+        rem &= ~m;
     }
 }
 
@@ -370,7 +502,9 @@ __device__ __forceinline__ void drift_and_hash(int i, const State& S, const Grid
     }
     const uint32_t kk = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
     key[i] = kk;
-    atomicAdd(&counts[kk], 1u);
+    int leader = 0, rank = 0, size = 1;
+    wave_group(kk, &leader, &rank, &size);
+    if (rank == 0) atomicAdd(&counts[kk], (uint32_t)size);
     if (outside) atomicOr(flags, kFlagOutside);
     if (nonfinite) atomicOr(flags, kFlagNonFinite);
 }
@@ -484,8 +618,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int n, const uint32_t* __res
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const uint32_t k = key[i];
-    const uint32_t old = atomicSub(&counts[k], 1u);
-    tmp[start[k] + old - 1u] = (uint32_t)i;
+    int leader = 0, rank = 0, size = 1;
+    wave_group(k, &leader, &rank, &size);
+    uint32_t old = 0;
+    if (rank == 0) old = atomicSub(&counts[k], (uint32_t)size);
+    old = (uint32_t)__shfl((int)old, leader, 64);
+    // the group takes slots [start + old - size, start + old)
+    tmp[start[k] + old - (uint32_t)size + (uint32_t)rank] = (uint32_t)i;
 }
 
 // Stable order inside each cell: slot s holds particle i = tmp[s]; its final
@@ -599,9 +738,11 @@ __device__ __forceinline__ void finish_density(int i, double rho, const PairCons
 
 // Summation density (eq. 2) and, if with_eos, the Tait EOS (eq. eos) with
 // P = p / rho^2 packed for the momentum pass.  Also adds the number of
-// interactions |N(i)| (self included) to *pairs, reduced per wave so that
-// one integer atomic per wave keeps the total exact and cheap.
-template <int DIM, int KERNEL, typename T>
+// interactions |N(i)| (self included) to the block's own 64-bit counter
+// pairs[block]: each block owns its slot (plain read-modify-write, no
+// atomics; launches are stream-ordered), and block 0 records the number of
+// counters in pairs[-1] so that the reader can sum them.
+template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
                                                     const uint32_t* __restrict__ skey,
                                                     const typename Rec<T>::type* __restrict__ pos,
@@ -618,7 +759,7 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
         // The density terms are FP64 in both precisions: the EOS multiplies
         // density rounding by ~7 B / rho0 before it reaches the forces.
         double acc = 0.0;
-        for_each_neighbor<DIM, T>(G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+        for_each_neighbor<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
                                   [&](uint32_t j, const typename Rec<T>::type& rj,
                                       const Geom<T>& g) {
                                       const double q = sqrt(g.r2d) * C.inv_h_d;
@@ -630,7 +771,16 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(pairs, (unsigned long long)cnt);
+    __shared__ uint32_t wcnt[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
+        const int blk = xcd_block();
+        pairs[blk] += t;
+        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
+    }
 }
 
 // Momentum equation for fluid particles (walls: a = 0):
@@ -641,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
 //   diag != 0: per-block partial sums of m|u|^2/2 and m u into diag_part;
 //   drift = 1: open the next step (half kick, drift, wrap, hash and count),
 //              leaving v of the next step in u.
-template <int DIM, int KERNEL, typename T>
+template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_momentum(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
     const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
@@ -661,12 +811,17 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
             const typename Vec4<T>::type vi = vel[i];
             const typename Vec2<T>::type rpi = rp[i];
             T ax = C.g[0], ay = C.g[1], az = C.g[2];
-            for_each_neighbor<DIM, T>(
-                G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
-                [&](uint32_t j, const typename Rec<T>::type& rj, const Geom<T>& g) {
+            struct Pay {
+                typename Vec4<T>::type v;
+                typename Vec2<T>::type rp;
+            };
+            for_each_neighbor_p<DIM, SR, T>(
+                G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
+                [&](uint32_t j) { return Pay{vel[j], rp[j]}; },
+                [&](uint32_t j, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
                     if (j == (uint32_t)i) return;
-                    const typename Vec4<T>::type vj = vel[j];
-                    const typename Vec2<T>::type rpj = rp[j];
+                    const typename Vec4<T>::type vj = pj.v;
+                    const typename Vec2<T>::type rpj = pj.rp;
                     const T r2 = g.r2;
                     const T q = p_sqrt(r2) * C.inv_h;
                     const T F = kernel_f<KERNEL, T>(q, C.sigma_h2);
@@ -710,7 +865,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
 }
 
 // Neighbour counts (phase 1) and lists (phase 2) of sph_neighbors.
-template <int DIM, typename T>
+template <int DIM, int SR, typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_count(int n, Grid G, PairConst<T> C,
                                                       const uint32_t* __restrict__ skey,
                                                       const typename Rec<T>::type* __restrict__ pos,
@@ -721,12 +876,12 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count(int n, Grid G, PairConst<T
     if (i >= n) return;
     const typename Rec<T>::type ri = pos[i];
     uint32_t c = 0;
-    for_each_neighbor<DIM, T>(G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+    for_each_neighbor<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
                               [&](uint32_t, const typename Rec<T>::type&, const Geom<T>&) { ++c; });
     cnt[i] = c;
 }
 
-template <int DIM, typename T>
+template <int DIM, int SR, typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_fill(int n, Grid G, PairConst<T> C,
                                                      const uint32_t* __restrict__ skey,
                                                      const typename Rec<T>::type* __restrict__ pos,
@@ -739,7 +894,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill(int n, Grid G, PairConst<T>
     const typename Rec<T>::type ri = pos[i];
     int64_t w = off[i];
     const int64_t wend = off[i + 1];
-    for_each_neighbor<DIM, T>(G, C, skey[i], ri, pos, cstart, cend, (uint32_t)n,
+    for_each_neighbor<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
                               [&](uint32_t j, const typename Rec<T>::type&, const Geom<T>&) {
                                   if (w < wend) nbr[w++] = (int32_t)j;
                               });
