@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="tg512")
+    ap.add_argument("--cell-div", type=int, default=0,
+                    help="cells per support radius (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -267,6 +269,8 @@ def main():
     import sph_workloads as W
 
     wl = W.workload(args.workload)
+    if args.cell_div:
+        wl.params = wl.params.replace(cell_div=args.cell_div)
     print(f"# workload {wl.name}: {wl.description}; n={wl.state.n}", file=sys.stderr, flush=True)
     mixed = run_precision(sph, torch, wl, sph.FP32_MIXED, args.steps, args.warmup, True)
     print(f"# fp32-mixed: {mixed['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)

@@ -331,7 +331,13 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
     C.R2_d = 4.0 * h * h;
     C.inv_h_d = 1.0 / h;
     C.sigma_d = sigma;
-    for (int k = 0; k < 3; ++k) C.fix_scale[k] = G.cs[k] / (double)(1 << sph::kFixBits);
+    for (int k = 0; k < 3; ++k) {
+        C.fix_scale[k] = G.cs[k] / (double)(1 << sph::kFixBits);
+        C.fix_scale_f[k] = (float)C.fix_scale[k];
+    }
+    C.R2_lo = (float)(4.0 * h * h * (1.0 - 1e-5));
+    C.R2_hi = (float)(4.0 * h * h * (1.0 + 1e-5));
+    C.h = (T)h;
     C.inv_h = (T)(1.0 / h);
     C.sigma = (T)sigma;
     C.sigma_h2 = (T)(sigma / (h * h));

@@ -78,14 +78,18 @@ constexpr int kFixClamp = (1 << 29) - 1;  // offsets within 4 cells of the centr
 __device__ __forceinline__ double rec_mass(const double4& r) { return r.w; }
 __device__ __forceinline__ float rec_mass(const int4& r) { return __int_as_float(r.w); }
 
-// Separation of a candidate pair: r_ij in the pair precision, |r_ij|^2 in the
-// pair precision and in FP64 (the neighbour predicate and the density terms
-// use the FP64 value).
-template <typename T>
-struct Geom {
-    T d[3];
-    T r2;
-    double r2d;
+// Separation of an accepted pair: r_ij and |r_ij|^2 in the pair precision;
+// in mixed precision also the exact fixed-point difference, from which
+// geom_r2d() forms |r_ij|^2 in FP64 for the density terms.
+template <typename T> struct Geom;
+template <> struct Geom<double> {
+    double d[3];
+    double r2;
+};
+template <> struct Geom<float> {
+    float d[3];
+    float r2;
+    int id[3];
 };
 template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
@@ -105,12 +109,25 @@ struct PairConst {
     T rho0, inv_rho0, B;  // Tait: p = B((rho/rho0)^7 - 1)
     double rho0_d, B_d;   // the same in FP64 (per-particle EOS)
     T L[3];        // box lengths (periodic image shifts)
+    T h;           // smoothing length
     double R2_d;         // (2h)^2 in FP64: the neighbour predicate
     double inv_h_d, sigma_d;  // FP64 density terms
     double fix_scale[3];      // cell size / 2^27: one fixed-point unit
+    float fix_scale_f[3];     // the same in FP32
+    float R2_lo, R2_hi;       // (2h)^2 (1 -+ 1e-5): FP32 test band, FP64 inside it
     T sigma_h4;    // sigma / h^4 (adjoint only)
     T b7;          // 7 B / rho0 = dp/drho at rho0 (adjoint only)
 };
+
+__device__ __forceinline__ double geom_r2d(const Geom<double>& g, const PairConst<double>&) {
+    return g.r2;
+}
+__device__ __forceinline__ double geom_r2d(const Geom<float>& g, const PairConst<float>& C) {
+    const double x = (double)g.id[0] * C.fix_scale[0];
+    const double y = (double)g.id[1] * C.fix_scale[1];
+    const double z = (double)g.id[2] * C.fix_scale[2];
+    return x * x + y * y + z * z;
+}
 
 // ---------------------------------------------------------------------------
 // Precision-generic helpers.  Mixed precision uses the hardware square root
@@ -119,17 +136,34 @@ __device__ __forceinline__ float p_sqrt(float x) { return __builtin_amdgcn_sqrtf
 __device__ __forceinline__ double p_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float p_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double p_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float p_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double p_rsqrt(double x) { return 1.0 / sqrt(x); }
+
+// FP64 square root for the mixed-precision density terms: an FP32 seed and
+// one Newton step, relative error ~2e-14 (sqrt(0) = 0).  The FP64 path uses
+// the correctly rounded sqrt.
+__device__ __forceinline__ double sqrt_newton(double x) {
+    const float s = __builtin_amdgcn_sqrtf((float)x);
+    const double sd = (double)s;
+    const double res = fma(-sd, sd, x);
+    const double corr = res * (0.5 * (double)__builtin_amdgcn_rcpf(s));
+    return s > 0.f ? sd + corr : 0.0;
+}
+__device__ __forceinline__ double density_sqrt(double x, float) { return sqrt_newton(x); }
+__device__ __forceinline__ double density_sqrt(double x, double) { return sqrt(x); }
 
 // Smoothing kernel W(q) = sigma w(q), q = r/h, support q < 2.
 //   cubic spline (M4):  1 - 1.5 q^2 + 0.75 q^3 (q < 1);  0.25 (2 - q)^3 (q < 2)
 //   Wendland C2:        (1 - q/2)^4 (2 q + 1)
+// The cubic spline is evaluated as 0.25 (2-q)^3 - (1-q)_+^3, the same
+// polynomial as 1 - 1.5 q^2 + 0.75 q^3 on q < 1 without a second branch.
 template <int KERNEL, typename T>
 __device__ __forceinline__ T kernel_w(T q, T sigma) {
     if (KERNEL == 0) {
-        const T t = T(2) - q;
-        const T outer = T(0.25) * t * t * t;
-        const T inner = T(1) - q * q * (T(1.5) - T(0.75) * q);
-        return sigma * (q < T(1) ? inner : outer);
+        const T t2 = T(2) - q;
+        T t1 = T(1) - q;
+        t1 = t1 > T(0) ? t1 : T(0);
+        return sigma * (T(0.25) * t2 * t2 * t2 - t1 * t1 * t1);
     } else {
         const T t = T(1) - T(0.5) * q;
         const T t2 = t * t;
@@ -149,6 +183,23 @@ __device__ __forceinline__ T kernel_f(T q, T sigma_h2) {
     } else {
         const T t = T(1) - T(0.5) * q;
         return T(-5) * sigma_h2 * t * t * t;
+    }
+}
+
+// F = (dW/dr)/r from |r|^2 with one reciprocal square root: rinv = 1/|r|,
+// q = |r| / h, 1/q = h rinv (rinv = 0 at r = 0, where F r = 0 anyway).
+template <int KERNEL, typename T>
+__device__ __forceinline__ T kernel_f_r2(T r2, const PairConst<T>& C) {
+    const T rinv = r2 > T(0) ? p_rsqrt(r2) : T(0);
+    const T q = r2 * rinv * C.inv_h;
+    if (KERNEL == 0) {
+        const T t = T(2) - q;
+        const T inner = C.sigma_h2 * (T(-3) + T(2.25) * q);
+        const T outer = T(-0.75) * C.sigma_h2 * t * t * (C.h * rinv);
+        return q < T(1) ? inner : outer;
+    } else {
+        const T t = T(1) - T(0.5) * q;
+        return T(-5) * C.sigma_h2 * t * t * t;
     }
 }
 
@@ -281,11 +332,16 @@ __device__ __forceinline__ double sep_axis(const int4& ri, const int4& rj, int k
 }
 
 // Test of one candidate j at x stencil offset ox: calls f if |r_ij| < 2h.
+// FP64: the test on fl(x_i - x_j) (minus the periodic shift).  Mixed
+// precision: the separation is an exact integer difference; it is tested in
+// FP32 and, only inside a band of +-1e-5 around (2h)^2 (well above the FP32
+// rounding of |r|^2), again in FP64, so the decision is the FP64 predicate,
+// and it stays exactly symmetric (swapping i and j negates the integers).
 template <int DIM, typename T, typename P, typename Fn>
-__device__ __forceinline__ void visit_candidate(uint32_t j, const typename Rec<T>::type& rj,
-                                                const P& pay, const typename Rec<T>::type& ri,
-                                                int ox, int wx, int oy, int wy, int oz, int wz,
-                                                const PairConst<T>& C, Fn& f) {
+__device__ __forceinline__ void visit_candidate(uint32_t j, const double4& rj, const P& pay,
+                                                const double4& ri, int ox, int wx, int oy,
+                                                int wy, int oz, int wz,
+                                                const PairConst<double>& C, Fn& f) {
     const double dx = sep_axis(ri, rj, 0, ox, wx, C);
     const double dy = sep_axis(ri, rj, 1, oy, wy, C);
     double r2 = dx * dx + dy * dy;
@@ -295,14 +351,30 @@ __device__ __forceinline__ void visit_candidate(uint32_t j, const typename Rec<T
         r2 += dz * dz;
     }
     if (r2 < C.R2_d) {
-        Geom<T> g;
-        g.d[0] = (T)dx;
-        g.d[1] = (T)dy;
-        g.d[2] = (T)dz;
-        g.r2 = (T)r2;
-        g.r2d = r2;
+        Geom<double> g;
+        g.d[0] = dx;
+        g.d[1] = dy;
+        g.d[2] = dz;
+        g.r2 = r2;
         f(j, rj, pay, g);
     }
+}
+
+template <int DIM, typename T, typename P, typename Fn>
+__device__ __forceinline__ void visit_candidate(uint32_t j, const int4& rj, const P& pay,
+                                                const int4& ri, int ox, int, int oy, int,
+                                                int oz, int, const PairConst<float>& C, Fn& f) {
+    Geom<float> g;
+    g.id[0] = (ri.x - rj.x) - ox * (1 << kFixBits);
+    g.id[1] = (ri.y - rj.y) - oy * (1 << kFixBits);
+    g.id[2] = DIM == 3 ? (ri.z - rj.z) - oz * (1 << kFixBits) : 0;
+    g.d[0] = (float)g.id[0] * C.fix_scale_f[0];
+    g.d[1] = (float)g.id[1] * C.fix_scale_f[1];
+    g.d[2] = DIM == 3 ? (float)g.id[2] * C.fix_scale_f[2] : 0.f;
+    g.r2 = g.d[0] * g.d[0] + g.d[1] * g.d[1] + (DIM == 3 ? g.d[2] * g.d[2] : 0.f);
+    if (g.r2 >= C.R2_hi) return;
+    if (g.r2 >= C.R2_lo && geom_r2d(g, C) >= C.R2_d) return;
+    f(j, rj, pay, g);
 }
 
 // No per-candidate payload beyond the position record.
@@ -762,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
         for_each_neighbor<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
                                   [&](uint32_t j, const typename Rec<T>::type& rj,
                                       const Geom<T>& g) {
-                                      const double q = sqrt(g.r2d) * C.inv_h_d;
+                                      const double q = density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
                                       acc += (double)rec_mass(rj) *
                                              kernel_w<KERNEL, double>(q, C.sigma_d);
                                       ++cnt;
@@ -823,8 +895,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
                     const typename Vec4<T>::type vj = pj.v;
                     const typename Vec2<T>::type rpj = pj.rp;
                     const T r2 = g.r2;
-                    const T q = p_sqrt(r2) * C.inv_h;
-                    const T F = kernel_f<KERNEL, T>(q, C.sigma_h2);
+                    const T F = kernel_f_r2<KERNEL, T>(r2, C);
                     const T pres = -(rpi.y + rpj.y) * F;
                     const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
                     const T mj = rec_mass(rj);
