@@ -43,19 +43,27 @@ FLOPS_PER_PAIR = {
     ("density", 2): 19, ("density", 3): 20,
     ("momentum", 2): 34, ("momentum", 3): 42,
 }
+# Neighbour-list build: per candidate pair tested (every particle of the
+# stencil cells of i's cell): the separation (dim), |r|^2 (2 dim - 1).
+FLOPS_PER_TEST = {2: 5, 3: 8}
 
 
 def bytes_per_particle(kernel: str, dim: int, tsize: int) -> int:
     """Algorithmic bytes per particle of each step kernel: every array the
     kernel must touch, read or written once (neighbour re-reads served from
-    cache are not algorithmic traffic)."""
+    cache are not algorithmic traffic).  The neighbour lists (4 bytes per
+    interaction) are added per pair by list_bytes()."""
     d, T = dim, tsize
+    R = 16 if T == 4 else 32  # pair record: int4 offsets + mass / double4
+    if kernel == "nlist":
+        # in: record, key; out: neighbour count
+        return R + 4 + 4
     if kernel == "density":
-        # in: (delta, m), key; out: rho, p, (rho, P)
-        return (d + 1) * T + 4 + 2 * T + 2 * T
+        # in: record, count; out: rho, p, (rho, P)
+        return R + 4 + 2 * T + 2 * T
     if kernel == "momentum":
-        # in: (delta, m), v, (rho, P), type, key, u (f64); out: a, u (f64)
-        return (d + 1) * T + d * T + 2 * T + 1 + 4 + 8 * d + d * T + 8 * d
+        # in: record, count, v, (rho, P), type, u (f64); out: a, u (f64), key
+        return R + 4 + 4 * T + 2 * T + 1 + 8 * d + d * T + 8 * d + 4
     if kernel == "drift_hash":
         # in: x, u (f64), a, type; out: x, v (f64), key, cell count
         return 16 * d + d * T + 1 + 16 * d + 4 + 4
@@ -113,6 +121,8 @@ def run_precision(sph, torch, wl, prec, steps, warmup, timing):
     res = {"seconds": t1 - t0, "ms_per_step": 1e3 * (t1 - t0) / steps,
            "interactions": inter, "interactions_per_s": inter / (t1 - t0)}
     if timing:
+        res["pair_tests"] = stencil_tests(sph, prm, dp.x.cpu().numpy())
+    if timing:
         # second timed region with every kernel bracketed by HIP events on the
         # library's stream: per-kernel average durations
         sph.timer_read(reset=True)
@@ -133,7 +143,37 @@ def run_precision(sph, torch, wl, prec, steps, warmup, timing):
     return res
 
 
-def roofline(res, wl, prec, steps):
+def stencil_tests(sph, prm, x) -> int:
+    """Candidate pairs the list build tests in one launch: for every particle,
+    the particles of the (2S+1)^dim stencil cells of its cell (host count
+    from the cell occupancy of positions x)."""
+    import numpy as np
+    nc, _ = sph.grid(prm)
+    dim, S = prm.dim, prm.cell_div
+    cells = []
+    for k in range(dim):
+        cs = (prm.hi[k] - prm.lo[k]) / nc[k]
+        c = np.floor((x[k] - prm.lo[k]) / cs).astype(np.int64)
+        cells.append(np.clip(c, 0, nc[k] - 1))
+    occ = np.zeros(tuple(nc[:dim]), np.int64)
+    np.add.at(occ, tuple(cells), 1)
+    M = np.zeros_like(occ)
+    for off in np.ndindex(*([2 * S + 1] * dim)):
+        sh = occ
+        for k in range(dim):
+            o = off[k] - S
+            if o == 0:
+                continue
+            sh = np.roll(sh, -o, axis=k)  # sh[c] = occ[c + o]
+            if not prm.periodic[k]:
+                idx = [slice(None)] * dim
+                idx[k] = slice(nc[k] - o, nc[k]) if o > 0 else slice(0, -o)
+                sh[tuple(idx)] = 0
+        M += sh
+    return int((occ * M).sum())
+
+
+def roofline(res, wl, prec, steps, tests=None):
     """Roofline entry of the dominant kernel of the step."""
     kus = res["kernels_us"]
     launches = res["kernels_launches"]
@@ -144,9 +184,14 @@ def roofline(res, wl, prec, steps):
     tsize = 4 if prec == 1 else 8
     inter_per_launch = res["interactions_timed"] / steps
     nbytes = bytes_per_particle(dom, dim, tsize) * n
-    if dom in ("density", "momentum"):
-        pairs = inter_per_launch if dom == "density" else inter_per_launch - n
-        flops = FLOPS_PER_PAIR[(dom, dim)] * pairs
+    if dom in ("nlist", "density", "momentum"):
+        nbytes += 4 * inter_per_launch  # the neighbour lists, written or read once
+    if dom in ("nlist", "density", "momentum"):
+        if dom == "nlist":
+            flops = FLOPS_PER_TEST[dim] * tests
+        else:
+            pairs = inter_per_launch if dom == "density" else inter_per_launch - n
+            flops = FLOPS_PER_PAIR[(dom, dim)] * pairs
         intensity = flops / nbytes
         ridge = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
         if intensity >= ridge:
@@ -165,6 +210,9 @@ def roofline(res, wl, prec, steps):
     out["kernel"] = dom
     out["avg_launch_us"] = kus[dom]
     out["bytes_per_launch"] = nbytes
+    out["interactions_per_launch"] = inter_per_launch
+    if dom == "nlist":
+        out["pair_tests_per_launch"] = tests
     out["traffic"] = traffic_from_profile(dom, wl.name)
     return out
 
@@ -278,7 +326,7 @@ def main():
     if not args.no_fp64:
         fp64 = run_precision(sph, torch, wl, sph.FP64, args.steps, args.warmup, True)
         print(f"# fp64: {fp64['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
-    rl = roofline(mixed, wl, sph.FP32_MIXED, args.steps)
+    rl = roofline(mixed, wl, sph.FP32_MIXED, args.steps, mixed["pair_tests"])
     adj = None
     if not args.no_adjoint:
         adj = adjoint_ratio(sph, torch)

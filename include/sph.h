@@ -67,7 +67,13 @@ typedef struct {
     int32_t precision;    /* sph_precision */
     int32_t cell_div;     /* cells per support radius along an axis: 1 or 2 */
     int32_t periodic[3];  /* 1 if the axis is periodic */
-    int32_t reserved;     /* must be 0 */
+    int32_t nbr_cap;      /* per-particle neighbour-list capacity of the pair
+                           * passes: 0 = default (64 in 2D, 192 in 3D), > 0 =
+                           * that many rounded up to a multiple of 4 (at most
+                           * 4096), < 0 = no lists (every
+                           * pass walks the cells).  A particle with more
+                           * neighbours than the capacity is walked; results
+                           * do not depend on it. */
     double h;             /* smoothing length, > 0 */
     double rho0;          /* reference density, > 0 */
     double c0;            /* reference speed of sound, > 0 */

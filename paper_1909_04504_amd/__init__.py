@@ -36,7 +36,7 @@ class SphError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("dim", _i32), ("kernel", _i32), ("precision", _i32), ("cell_div", _i32),
-                ("periodic", _i32 * 3), ("reserved", _i32),
+                ("periodic", _i32 * 3), ("nbr_cap", _i32),
                 ("h", _d), ("rho0", _d), ("c0", _d), ("nu", _d), ("eta", _d), ("dt", _d),
                 ("g", _d * 3), ("lo", _d * 3), ("hi", _d * 3)]
 
@@ -87,14 +87,15 @@ def _rc(code: int):
         raise SphError(code, lib().sph_last_error().decode())
 
 
-def make_params(p, precision: int = FP64) -> Params:
-    """C parameter struct from a sph_workloads.Params-like object."""
+def make_params(p, precision: int = FP64, nbr_cap: int = 0) -> Params:
+    """C parameter struct from a sph_workloads.Params-like object.  nbr_cap:
+    neighbour-list capacity per particle (0 default, < 0 cell walks only)."""
     c = Params()
     c.dim, c.kernel, c.precision, c.cell_div = p.dim, p.kernel, precision, p.cell_div
     for k in range(3):
         c.periodic[k] = int(p.periodic[k])
         c.g[k], c.lo[k], c.hi[k] = float(p.g[k]), float(p.lo[k]), float(p.hi[k])
-    c.reserved = 0
+    c.nbr_cap = int(nbr_cap)
     c.h, c.rho0, c.c0, c.nu, c.eta, c.dt = p.h, p.rho0, p.c0, p.nu, p.eta, p.dt
     return c
 

@@ -7,13 +7,18 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "sph.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "sph_kernels.hpp"), os.path.join(ROOT, "include", "sph.h")]
+DEPS = [SRC, os.path.join(HERE, "csrc", "sph_kernels.hpp"),
+        os.path.join(HERE, "csrc", "sph_adjoint.hpp"), os.path.join(ROOT, "include", "sph.h")]
 LIB = os.path.join(HERE, "libsph_mi355x.so")
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression, so an inlined
+    # helper rounds the same wherever it is used (the pair arithmetic is
+    # bitwise the same whether a neighbour comes from a list or a cell walk)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -54,12 +54,12 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + sph::kBlock - 1) 
 enum KernelId {
     K_FILL, K_HASH, K_CHUNK_SUM, K_CHUNK_SCAN, K_SCATTER, K_RANK_GATHER, K_PACK, K_DENSITY,
     K_MOMENTUM, K_EOS, K_NBR_COUNT, K_NBR_FILL, K_CELL_RANGES, K_COPY, K_DIAG, K_ADJ_SEED,
-    K_ADJ_PAIR1, K_ADJ_PAIR2, K_ADJ_REDUCE, K_ADJ_KICK, K_COUNT
+    K_ADJ_PAIR1, K_ADJ_PAIR2, K_ADJ_REDUCE, K_ADJ_KICK, K_NLIST, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "fill", "drift_hash", "chunk_sum", "chunk_scan", "scatter", "rank_gather", "pack",
     "density", "momentum", "eos", "nbr_count", "nbr_fill", "cell_ranges", "copy_state", "diag",
-    "adj_seed", "adj_pair1", "adj_pair2", "adj_reduce", "adj_kick"};
+    "adj_seed", "adj_pair1", "adj_pair2", "adj_reduce", "adj_kick", "nlist"};
 
 struct Timer {
     bool on = false;
@@ -75,8 +75,10 @@ struct Timer {
             spare.pop_back();
             return e;
         }
+        // timing-only events: no system-scope fence (cache writeback and
+        // invalidation) around the bracketed launch
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         return e;
     }
     void fold() {
@@ -116,6 +118,8 @@ struct Timed {
 // ---------------------------------------------------------------------------
 // Validation
 
+constexpr int kMaxNbrCap = 4096;
+
 int check_params(const sph_params* p, bool need_dt) {
     if (!p) return fail(SPH_EINVAL, "params is NULL");
     if (p->dim != 2 && p->dim != 3) return fail(SPH_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
@@ -124,7 +128,8 @@ int check_params(const sph_params* p, bool need_dt) {
     if (p->precision != SPH_FP64 && p->precision != SPH_FP32_MIXED)
         return fail(SPH_EINVAL, "unknown precision %d", p->precision);
     if (p->cell_div != 1 && p->cell_div != 2) return fail(SPH_EINVAL, "cell_div must be 1 or 2");
-    if (p->reserved != 0) return fail(SPH_EINVAL, "reserved field must be 0");
+    if (p->nbr_cap > kMaxNbrCap)
+        return fail(SPH_EINVAL, "nbr_cap must be at most %d (got %d)", kMaxNbrCap, p->nbr_cap);
     if (!(p->h > 0) || !std::isfinite(p->h)) return fail(SPH_EINVAL, "h must be > 0");
     if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(SPH_EINVAL, "rho0 must be > 0");
     if (!(p->c0 > 0) || !std::isfinite(p->c0)) return fail(SPH_EINVAL, "c0 must be > 0");
@@ -172,7 +177,30 @@ int make_grid(const sph_params* p, sph::Grid* G, int64_t* ncells) {
         G->lo[k] = p->lo[k];
         G->periodic[k] = p->periodic[k];
     }
+    for (int a = 0; a < 2; ++a) sph::div_magic((uint32_t)G->nc[a], &G->dmag[a], &G->dsh1[a], &G->dsh2[a]);
     return SPH_OK;
+}
+
+// Largest particle count whose slot indices fit beside the stencil code of
+// a list entry.
+template <int DIM, int SR, typename T>
+uint32_t list_max_n() {
+    return sph::NbrCode<DIM, SR, T>::kMaxN;
+}
+uint32_t list_max_n(const sph_params* p) {
+    const bool f64 = p->precision == SPH_FP64, s2 = p->cell_div == 2;
+    if (p->dim == 2)
+        return f64 ? (s2 ? list_max_n<2, 2, double>() : list_max_n<2, 1, double>())
+                   : (s2 ? list_max_n<2, 2, float>() : list_max_n<2, 1, float>());
+    return f64 ? (s2 ? list_max_n<3, 2, double>() : list_max_n<3, 1, double>())
+               : (s2 ? list_max_n<3, 2, float>() : list_max_n<3, 1, float>());
+}
+
+// Neighbour-list capacity per particle (0: no lists).
+uint32_t list_cap(const sph_params* p, int64_t n) {
+    if (p->nbr_cap < 0 || n > (int64_t)list_max_n(p)) return 0;
+    if (p->nbr_cap > 0) return (uint32_t)((p->nbr_cap + 3) & ~3);
+    return p->dim == 2 ? 64u : 192u;
 }
 
 int check_particles(const sph_params* p, const sph_particles* pa) {
@@ -201,7 +229,8 @@ struct SlotOff {
 };
 
 struct Layout {
-    size_t flags, counts, start, chunks, key, tmp, perm, skey, ncnt;
+    size_t flags, counts, start, chunks, key, tmp, perm, skey, ncnt, lcnt, list;
+    uint32_t cap;
     StateOff s1, s2;
     size_t pos, vel, rp, diag;
     // adjoint (present when adj_k > 0; the tape is the last region)
@@ -213,6 +242,18 @@ struct Layout {
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Launch shape of k_nlist: consecutive cells per wave so that there are at
+// most 16384 waves (two per SIMD slot of the chip at full occupancy): each
+// wave then overlaps the range loads of its next cell with the current one.
+void nlist_grid(int64_t ncells, unsigned* blocks, uint32_t* cells_per_wave) {
+    const int64_t max_waves = 16384;
+    int64_t cpw = (ncells + max_waves - 1) / max_waves;
+    if (cpw < 1) cpw = 1;
+    const int64_t waves = (ncells + cpw - 1) / cpw;
+    *blocks = (unsigned)((waves + sph::kBlock / 64 - 1) / (sph::kBlock / 64));
+    *cells_per_wave = (uint32_t)cpw;
+}
 
 Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k) {
     Layout L;
@@ -240,8 +281,11 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
     const int64_t longest = (ncells + 1 > n + 1) ? ncells + 1 : n + 1;
     const size_t nchunks = (size_t)((longest + sph::kScanChunk - 1) / sph::kScanChunk);
     // header (flag word at 0, number of interaction counters at 8), then one
-    // 64-bit interaction counter per density block from offset 16
-    L.flags = take(16 + 8 * (size_t)blocks_for(n));
+    // 64-bit interaction counter per k_nlist block from offset 16
+    unsigned nl_blocks;
+    uint32_t nl_cpw;
+    nlist_grid(ncells, &nl_blocks, &nl_cpw);
+    L.flags = take(16 + 8 * (size_t)nl_blocks);
     L.counts = take(4 * (size_t)ncells);
     L.start = take(4 * ((size_t)ncells + 1));
     L.chunks = take(8 * nchunks);
@@ -250,6 +294,10 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
     L.perm = take(4 * N);
     L.skey = take(4 * N);
     L.ncnt = take(4 * N);
+    L.cap = list_cap(p, n);
+    L.lcnt = take(4 * N);
+    L.list = take(4 * (size_t)L.cap * (size_t)sph::kListTile *
+                  ((N + sph::kListTile - 1) / sph::kListTile));
     L.s1 = take_state();
     L.pos = take(4 * T * N);
     L.vel = take(4 * T * N);
@@ -382,6 +430,8 @@ struct Engine {
     uint32_t* key() const { return (uint32_t*)(ws + L.key); }
     uint32_t* tmp() const { return (uint32_t*)(ws + L.tmp); }
     uint32_t* ncnt() const { return (uint32_t*)(ws + L.ncnt); }
+    uint32_t* lcnt() const { return (uint32_t*)(ws + L.lcnt); }
+    uint32_t* list() const { return (uint32_t*)(ws + L.list); }
 
     // Pair records and sort results of the current evaluation: the default
     // buffers, or one slot of the adjoint's recompute tape.
@@ -475,11 +525,31 @@ struct Engine {
         return launch_check("k_rank_gather");
     }
 
+    // Neighbour lists of the current records (count_pairs: add the number
+    // of interactions to the counters).  Every pair pass reads the lists
+    // built last, so each change of records is followed by this launch.
+    int nlist(const uint32_t* cs, const uint32_t* ce, bool count_pairs) {
+        unsigned nb;
+        uint32_t cpw;
+        nlist_grid(ncells, &nb, &cpw);
+        Timed t_(K_NLIST, st);
+        with_reach([&](auto R) {
+            sph::k_nlist<DIM, decltype(R)::value, T><<<nb, sph::kBlock, 0, st>>>(
+                n, (uint32_t)ncells, cpw, G, C, skey(), pos(), cs, ce, L.cap, list(), lcnt(),
+                count_pairs ? 1 : 0, pairs());
+        });
+        return launch_check("k_nlist");
+    }
+    const uint32_t* list_or_null() const { return L.cap ? list() : nullptr; }
+
+    // Lists of the current records, then the density over them.
     int density(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_eos) {
+        SPH_TRY(nlist(cs, ce, true));
         Timed t_(K_DENSITY, st);
         with_reach([&](auto R) {
             sph::k_density<DIM, decltype(R)::value, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
-                n, G, C, skey(), pos(), cs, ce, (T*)s.rho, (T*)s.p, rp(), with_eos ? 1 : 0, pairs());
+                n, G, C, skey(), pos(), cs, ce, list_or_null(), lcnt(), L.cap, (T*)s.rho,
+                (T*)s.p, rp(), with_eos ? 1 : 0);
         });
         return launch_check("k_density");
     }
@@ -494,7 +564,8 @@ struct Engine {
             Timed t_(K_MOMENTUM, st);
             with_reach([&](auto R) {
                 sph::k_momentum<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
-                    n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, s, kick ? 1 : 0,
+                    n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, list_or_null(), lcnt(),
+                    L.cap, s, kick ? 1 : 0,
                     drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(), flags(), part);
             });
             SPH_TRY(launch_check("k_momentum"));
@@ -540,6 +611,7 @@ struct Engine {
     int momentum_only(sph_particles* pa, const uint32_t* cs, const uint32_t* ce) {
         const sph::State user = user_state(pa);
         SPH_TRY(pack(user, true));
+        SPH_TRY(nlist(cs, ce, false));
         return momentum(user, cs, ce, false);
     }
 
@@ -609,8 +681,9 @@ struct Engine {
     // *dJ, at the evaluation whose records are current; lhat = lam_a +
     // hdt lam_u (fluid), read through `gather` (identity if null).
     int adjoint_rhs(const double* lam_u, const double* lam_a, int64_t ld, double hdt,
-                    const uint8_t* type, const uint32_t* gather, double* dJ) {
+                    const uint8_t* type, const uint32_t* gather, double* dJ, bool build_list) {
         const unsigned nb = blocks_for(n);
+        if (build_list) SPH_TRY(nlist(start(), start() + 1, false));
         V4* lhat = (V4*)(ws + L.lhat);
         double* lxd = (double*)(ws + L.lxd);
         double* lvd = (double*)(ws + L.lvd);
@@ -627,8 +700,8 @@ struct Engine {
             Timed t_(K_ADJ_PAIR1, st);
             with_reach([&](auto R) {
                 sph::k_adj_pair1<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
-                    n, G, C, skey(), pos(), vel(), rp(), lhat, start(), start() + 1, lxd, lvd,
-                    lrho, nup);
+                    n, G, C, skey(), pos(), vel(), rp(), lhat, start(), start() + 1,
+                    list_or_null(), lcnt(), L.cap, lxd, lvd, lrho, nup);
             });
             SPH_TRY(launch_check("k_adj_pair1"));
         }
@@ -636,7 +709,8 @@ struct Engine {
             Timed t_(K_ADJ_PAIR2, st);
             with_reach([&](auto R) {
                 sph::k_adj_pair2<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
-                    n, G, C, skey(), pos(), lrho, start(), start() + 1, lxd);
+                    n, G, C, skey(), pos(), lrho, start(), start() + 1, list_or_null(), lcnt(),
+                    L.cap, lxd);
             });
             SPH_TRY(launch_check("k_adj_pair2"));
         }
@@ -670,7 +744,8 @@ struct Engine {
         for (int64_t s = k - 1; s >= 0; --s) {
             tape_records(s);
             double* out = s == 0 ? lam_out : bufs[s & 1];
-            SPH_TRY(adjoint_rhs(in + DIM * N, in + 2 * DIM * N, N, hdt, typetape, nullptr, dJ));
+            SPH_TRY(adjoint_rhs(in + DIM * N, in + 2 * DIM * N, N, hdt, typetape, nullptr, dJ,
+                                true));
             Timed t_(K_ADJ_KICK, st);
             sph::k_adj_kick<DIM><<<blocks_for(n), sph::kBlock, 0, st>>>(
                 n, in, (const double*)(ws + L.lxd), (const double*)(ws + L.lvd), typetape, perm(),
@@ -691,7 +766,7 @@ struct Engine {
         SPH_TRY(zero_counts());
         SPH_TRY(sort_into(user, s1, false, false));
         SPH_TRY(density(s1, start(), start() + 1, true));
-        SPH_TRY(adjoint_rhs(nullptr, lam_a, n, 0.0, s1.type, perm(), dJ));
+        SPH_TRY(adjoint_rhs(nullptr, lam_a, n, 0.0, s1.type, perm(), dJ, false));
         Timed t_(K_ADJ_KICK, st);
         sph::k_adj_accum<DIM><<<blocks_for(n), sph::kBlock, 0, st>>>(
             n, (const double*)(ws + L.lxd), (const double*)(ws + L.lvd), s1.type, perm(), lam_x,

@@ -82,6 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
     const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
     const typename Vec2<T>::type* __restrict__ rp, const typename Vec4<T>::type* __restrict__ lhat,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap,
     double* __restrict__ lx, double* __restrict__ lv, T* __restrict__ lrho,
     double* __restrict__ nupart) {
     const int i = xcd_block() * kBlock + threadIdx.x;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
         typename Vec4<T>::type l;
     };
     for_each_neighbor_p<DIM, SR, T>(
-        G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
+        i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
         [&](uint32_t j) { return Pay{vel[j], rp[j], lhat[j]}; },
         [&](uint32_t j, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
             const T r2 = g.r2;
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair2(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
     const typename Rec<T>::type* __restrict__ pos, const T* __restrict__ lrho,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap,
     double* __restrict__ lx) {
     const int i = xcd_block() * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -174,7 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair2(
     const T mi = rec_mass(ri);
     T ax = 0, ay = 0, az = 0;
     for_each_neighbor_p<DIM, SR, T>(
-        G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n, [&](uint32_t j) { return lrho[j]; },
+        i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
+        [&](uint32_t j) { return lrho[j]; },
         [&](uint32_t j, const typename Rec<T>::type& rj, const T& lrj, const Geom<T>& g) {
             if (j == (uint32_t)i || g.r2 == T(0)) return;
             const T q = p_sqrt(g.r2) * C.inv_h;

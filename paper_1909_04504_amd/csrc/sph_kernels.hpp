@@ -48,7 +48,23 @@ struct Grid {
     double lo[3];
     double L[3];
     double cs[3];
+    // division of a key by nc[0] and of the quotient by nc[1] by multiply
+    // and shift (Granlund and Montgomery, 1994): magic, shift 1, shift 2
+    uint32_t dmag[2];
+    int dsh1[2], dsh2[2];
 };
+
+// Magic numbers of unsigned 32-bit division by d >= 1 (round-up method with
+// the add step): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1 (mod
+// 2^32), and n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0) with
+// t = mulhi(m, n), exact for every n < 2^32.
+inline void div_magic(uint32_t d, uint32_t* m, int* s1, int* s2) {
+    int l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+    *m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+    *s1 = l < 1 ? l : 1;
+    *s2 = l - 1 > 0 ? l - 1 : 0;
+}
 
 // Particle state arrays (device pointers); a, rho, p are of the pair type T.
 struct State {
@@ -226,11 +242,16 @@ __device__ __forceinline__ int xcd_block() {
     return x * per + (x < rem ? x : rem) + k;
 }
 
+__device__ __forceinline__ uint32_t div_by(uint32_t n, const Grid& G, int a) {
+    const uint32_t t = __umulhi(G.dmag[a], n);
+    return (t + ((n - t) >> G.dsh1[a])) >> G.dsh2[a];
+}
 __device__ __forceinline__ void decode_key(uint32_t key, const Grid& G, int c[3]) {
-    c[0] = (int)(key % (uint32_t)G.nc[0]);
-    const uint32_t t = key / (uint32_t)G.nc[0];
-    c[1] = (int)(t % (uint32_t)G.nc[1]);
-    c[2] = (int)(t / (uint32_t)G.nc[1]);
+    const uint32_t q = div_by(key, G, 0);
+    c[0] = (int)(key - q * (uint32_t)G.nc[0]);
+    const uint32_t r = div_by(q, G, 1);
+    c[1] = (int)(q - r * (uint32_t)G.nc[1]);
+    c[2] = (int)r;
 }
 
 // cell coordinate clamp(floor((x - lo)/cs), 0, nc-1); NaN goes to 0.  A
@@ -316,54 +337,29 @@ __device__ __forceinline__ int4 make_rec<float>(const double* x, const int* c, d
     return r;
 }
 
-// Per-axis separation of record rj from ri for the stencil offset o / wrap.
-__device__ __forceinline__ double sep_axis(const double4& ri, const double4& rj, int k, int o,
-                                           int wrap, const PairConst<double>& C) {
-    const double di = k == 0 ? ri.x : (k == 1 ? ri.y : ri.z);
-    const double dj = k == 0 ? rj.x : (k == 1 ? rj.y : rj.z);
-    (void)o;
-    return (di - dj) - (wrap == 0 ? 0.0 : (wrap < 0 ? -C.L[k] : C.L[k]));
+// Pair geometry for candidate j of particle i.
+//  * FP64: r_ij = fl(x_i - x_j) minus the periodic shift w L of a wrapped
+//    stencil cell (w in {-1, 0, 1} per axis).
+//  * Mixed precision: r_ij = (k_i - k_j - o 2^27) fixed-point units, o the
+//    stencil offset of j's cell (an exact integer), converted to FP32; the
+//    integers are kept for the FP64 |r|^2 of the density terms.
+template <int DIM>
+__device__ __forceinline__ Geom<double> pair_geom(const double4& ri, const double4& rj, int, int,
+                                                  int, int wx, int wy, int wz,
+                                                  const PairConst<double>& C) {
+    auto shift = [&](int w, int k) { return w == 0 ? 0.0 : (w < 0 ? -C.L[k] : C.L[k]); };
+    Geom<double> g;
+    g.d[0] = (ri.x - rj.x) - shift(wx, 0);
+    g.d[1] = (ri.y - rj.y) - shift(wy, 1);
+    g.d[2] = DIM == 3 ? (ri.z - rj.z) - shift(wz, 2) : 0.0;
+    g.r2 = g.d[0] * g.d[0] + g.d[1] * g.d[1];
+    if (DIM == 3) g.r2 += g.d[2] * g.d[2];
+    return g;
 }
-__device__ __forceinline__ double sep_axis(const int4& ri, const int4& rj, int k, int o, int,
-                                           const PairConst<float>& C) {
-    const int di = k == 0 ? ri.x : (k == 1 ? ri.y : ri.z);
-    const int dj = k == 0 ? rj.x : (k == 1 ? rj.y : rj.z);
-    return (double)((di - dj) - o * (1 << kFixBits)) * C.fix_scale[k];
-}
-
-// Test of one candidate j at x stencil offset ox: calls f if |r_ij| < 2h.
-// FP64: the test on fl(x_i - x_j) (minus the periodic shift).  Mixed
-// precision: the separation is an exact integer difference; it is tested in
-// FP32 and, only inside a band of +-1e-5 around (2h)^2 (well above the FP32
-// rounding of |r|^2), again in FP64, so the decision is the FP64 predicate,
-// and it stays exactly symmetric (swapping i and j negates the integers).
-template <int DIM, typename T, typename P, typename Fn>
-__device__ __forceinline__ void visit_candidate(uint32_t j, const double4& rj, const P& pay,
-                                                const double4& ri, int ox, int wx, int oy,
-                                                int wy, int oz, int wz,
-                                                const PairConst<double>& C, Fn& f) {
-    const double dx = sep_axis(ri, rj, 0, ox, wx, C);
-    const double dy = sep_axis(ri, rj, 1, oy, wy, C);
-    double r2 = dx * dx + dy * dy;
-    double dz = 0.0;
-    if (DIM == 3) {
-        dz = sep_axis(ri, rj, 2, oz, wz, C);
-        r2 += dz * dz;
-    }
-    if (r2 < C.R2_d) {
-        Geom<double> g;
-        g.d[0] = dx;
-        g.d[1] = dy;
-        g.d[2] = dz;
-        g.r2 = r2;
-        f(j, rj, pay, g);
-    }
-}
-
-template <int DIM, typename T, typename P, typename Fn>
-__device__ __forceinline__ void visit_candidate(uint32_t j, const int4& rj, const P& pay,
-                                                const int4& ri, int ox, int, int oy, int,
-                                                int oz, int, const PairConst<float>& C, Fn& f) {
+template <int DIM>
+__device__ __forceinline__ Geom<float> pair_geom(const int4& ri, const int4& rj, int ox, int oy,
+                                                 int oz, int, int, int,
+                                                 const PairConst<float>& C) {
     Geom<float> g;
     g.id[0] = (ri.x - rj.x) - ox * (1 << kFixBits);
     g.id[1] = (ri.y - rj.y) - oy * (1 << kFixBits);
@@ -372,9 +368,68 @@ __device__ __forceinline__ void visit_candidate(uint32_t j, const int4& rj, cons
     g.d[1] = (float)g.id[1] * C.fix_scale_f[1];
     g.d[2] = DIM == 3 ? (float)g.id[2] * C.fix_scale_f[2] : 0.f;
     g.r2 = g.d[0] * g.d[0] + g.d[1] * g.d[1] + (DIM == 3 ? g.d[2] * g.d[2] : 0.f);
-    if (g.r2 >= C.R2_hi) return;
-    if (g.r2 >= C.R2_lo && geom_r2d(g, C) >= C.R2_d) return;
-    f(j, rj, pay, g);
+    return g;
+}
+
+// Neighbour predicate |r_ij|^2 < (2h)^2, decided in FP64.  FP64: on the
+// separation itself.  Mixed precision: the FP32 |r|^2 decides outside a band
+// of +-1e-5 around (2h)^2 (well above its rounding error), the exact FP64
+// |r|^2 of the integer separation inside it; both are exactly symmetric
+// (swapping i and j negates the integers).
+__device__ __forceinline__ bool pair_accept(const Geom<double>& g, const PairConst<double>& C) {
+    return g.r2 < C.R2_d;
+}
+__device__ __forceinline__ bool pair_accept(const Geom<float>& g, const PairConst<float>& C) {
+    bool acc = g.r2 < C.R2_lo;
+    const bool band = !acc && g.r2 < C.R2_hi;
+    // the FP64 test runs only when some lane of the wave is inside the band
+    if (__ballot(band)) acc = acc || (band && geom_r2d(g, C) < C.R2_d);
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Stencil codes.  An accepted neighbour is stored as one 32-bit word,
+// (slot j << bits) | code, where the code gives what pair_geom needs besides
+// the two records: the stencil offsets o (mixed precision, base 2S+1 digits)
+// or the periodic images w (FP64, base 3 digits).
+template <int DIM, int SR, typename T>
+struct NbrCode {
+    static constexpr int NR = 2 * SR + 1;
+    static constexpr bool kFp64 = sizeof(T) == 8;
+    static constexpr int kCodes = kFp64 ? (DIM == 3 ? 27 : 9) : (DIM == 3 ? NR * NR * NR : NR * NR);
+    static constexpr int kBits = kCodes <= 16 ? 4 : (kCodes <= 32 ? 5 : (kCodes <= 64 ? 6 : 7));
+    static constexpr uint32_t kMask = (1u << kBits) - 1u;
+    // Largest particle count whose slots fit beside the code.
+    static constexpr uint32_t kMaxN = 1u << (32 - kBits);
+
+    // Part of the code fixed for one stencil row piece; the mixed-precision
+    // code adds the candidate's own x offset.
+    static __device__ __forceinline__ int row_base(int oy, int oz, int wx, int wy, int wz) {
+        if (kFp64) return (wx + 1) + 3 * ((wy + 1) + (DIM == 3 ? 3 * (wz + 1) : 0));
+        return SR + NR * ((oy + SR) + (DIM == 3 ? NR * (oz + SR) : 0));
+    }
+    static __device__ __forceinline__ uint32_t code(int base, int ox) {
+        return kFp64 ? (uint32_t)base : (uint32_t)(base + ox);
+    }
+    template <typename R>
+    static __device__ __forceinline__ Geom<T> geom(const R& ri, const R& rj, uint32_t c,
+                                                   const PairConst<T>& C) {
+        const int B = kFp64 ? 3 : NR, off = kFp64 ? 1 : SR;
+        const int a = (int)(c % (uint32_t)B) - off;
+        const uint32_t t = c / (uint32_t)B;
+        const int b = (int)(t % (uint32_t)B) - off;
+        const int d = DIM == 3 ? (int)(t / (uint32_t)B) - off : 0;
+        return kFp64 ? pair_geom<DIM>(ri, rj, 0, 0, 0, a, b, d, C)
+                     : pair_geom<DIM>(ri, rj, a, b, d, 0, 0, 0, C);
+    }
+};
+
+// Neighbour lists are stored in tiles of 64 particles (one wave): entry k of
+// sorted slot i at ((i / 64) cap + k) 64 + i % 64, so that the lanes of a
+// wave read entry k of their 64 lists as one contiguous 256-byte row.
+constexpr uint32_t kListTile = 64;
+__device__ __forceinline__ size_t list_column(uint32_t i, uint32_t cap) {
+    return ((size_t)(i / kListTile) * cap) * kListTile + (size_t)(i % kListTile);
 }
 
 // No per-candidate payload beyond the position record.
@@ -416,9 +471,9 @@ __device__ __forceinline__ void row_pieces(int cx, const Grid& G, int first[2], 
     }
 }
 
-// Neighbour loop: calls f(j, rec_j, payload_j, geom) for every sorted slot j
-// with |r_ij|^2 < (2h)^2 in the (2S+1)^dim stencil cells of i's cell (self
-// included), payload_j = load(j).
+// Cell walk: calls f(j, rec_j, payload_j, geom, code) for every sorted slot
+// j with |r_ij|^2 < (2h)^2 in the (2S+1)^dim stencil cells of i's cell (self
+// included), payload_j = load(j), code = j's stencil code.
 //  * The cells of one stencil row are adjacent in memory (row-major keys), so
 //    a row is walked as one slot range (two if it wraps a periodic x
 //    boundary).  A candidate's x offset comes from its own sorted key:
@@ -428,15 +483,15 @@ __device__ __forceinline__ void row_pieces(int cx, const Grid& G, int first[2], 
 //    payloads loaded ahead of the arithmetic, so each lane keeps several
 //    independent loads in flight instead of one dependent chain.
 template <int DIM, int S, typename T, typename Load, typename Fn>
-__device__ __forceinline__ void for_each_neighbor_p(const Grid& G, const PairConst<T>& C,
-                                                    uint32_t key,
-                                                    const typename Rec<T>::type& ri,
-                                                    const typename Rec<T>::type* __restrict__ pos,
-                                                    const uint32_t* __restrict__ skey,
-                                                    const uint32_t* __restrict__ cstart,
-                                                    const uint32_t* __restrict__ cend,
-                                                    uint32_t n, Load&& load, Fn&& f) {
+__device__ __forceinline__ void walk_pairs(const Grid& G, const PairConst<T>& C, uint32_t key,
+                                           const typename Rec<T>::type& ri,
+                                           const typename Rec<T>::type* __restrict__ pos,
+                                           const uint32_t* __restrict__ skey,
+                                           const uint32_t* __restrict__ cstart,
+                                           const uint32_t* __restrict__ cend, uint32_t n,
+                                           Load&& load, Fn&& f) {
     using R = typename Rec<T>::type;
+    using Code = NbrCode<DIM, S, T>;
     constexpr int NR = 2 * S + 1;
     int c[3];
     decode_key(key, G, c);
@@ -478,39 +533,85 @@ __device__ __forceinline__ void for_each_neighbor_p(const Grid& G, const PairCon
             for (int k = 0; k < 2; ++k) {
                 const int wx = wrap[k];
                 const int xoff = wx * G.nc[0] - xbase;
+                const int cb = Code::row_base(oy, oz, wx, wy, wz);
                 auto ox_of = [&](uint32_t j) { return (int)skey[j] + xoff; };
+                auto visit = [&](uint32_t j, const R& rj, const auto& pj, int ox) {
+                    const Geom<T> g = pair_geom<DIM>(ri, rj, ox, oy, oz, wx, wy, wz, C);
+                    if (pair_accept(g, C)) f(j, rj, pj, g, Code::code(cb, ox));
+                };
                 const uint32_t e = pe[yi][k];
                 uint32_t j = pb[yi][k];
                 for (; j + 4 <= e; j += 4) {
                     const R r0 = pos[j], r1 = pos[j + 1], r2 = pos[j + 2], r3 = pos[j + 3];
                     const int o0 = ox_of(j), o1 = ox_of(j + 1), o2 = ox_of(j + 2), o3 = ox_of(j + 3);
                     const auto p0 = load(j), p1 = load(j + 1), p2 = load(j + 2), p3 = load(j + 3);
-                    visit_candidate<DIM, T>(j, r0, p0, ri, o0, wx, oy, wy, oz, wz, C, f);
-                    visit_candidate<DIM, T>(j + 1, r1, p1, ri, o1, wx, oy, wy, oz, wz, C, f);
-                    visit_candidate<DIM, T>(j + 2, r2, p2, ri, o2, wx, oy, wy, oz, wz, C, f);
-                    visit_candidate<DIM, T>(j + 3, r3, p3, ri, o3, wx, oy, wy, oz, wz, C, f);
+                    visit(j, r0, p0, o0);
+                    visit(j + 1, r1, p1, o1);
+                    visit(j + 2, r2, p2, o2);
+                    visit(j + 3, r3, p3, o3);
                 }
                 for (; j < e; ++j) {
                     const R rj = pos[j];
                     const int oj = ox_of(j);
                     const auto pj = load(j);
-                    visit_candidate<DIM, T>(j, rj, pj, ri, oj, wx, oy, wy, oz, wz, C, f);
+                    visit(j, rj, pj, oj);
                 }
             }
         }
     }
 }
 
+// The neighbours of sorted slot i, in walk order: from its stored list when
+// it holds all of them (cnt <= cap), else by the cell walk.  Calls
+// f(j, rec_j, payload_j, geom) with the same geometry either way.
+template <int DIM, int S, typename T, typename Load, typename Fn>
+__device__ __forceinline__ void for_each_neighbor_p(
+    int i, const Grid& G, const PairConst<T>& C, const typename Rec<T>::type& ri,
+    const typename Rec<T>::type* __restrict__ pos, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, uint32_t n,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap,
+    Load&& load, Fn&& f) {
+    using R = typename Rec<T>::type;
+    using Code = NbrCode<DIM, S, T>;
+    const uint32_t cnt = list ? ncnt[i] : 0xffffffffu;
+    if (cnt <= cap) {
+        const uint32_t* __restrict__ col = list + list_column((uint32_t)i, cap);
+        // slot of entry e (clamped into [0, n), which a current list never needs)
+        auto slot = [&](uint32_t e) { return min(e >> Code::kBits, n - 1u); };
+        uint32_t k = 0;
+        for (; k + 4 <= cnt; k += 4) {
+            const uint32_t e0 = col[(k + 0) * kListTile], e1 = col[(k + 1) * kListTile];
+            const uint32_t e2 = col[(k + 2) * kListTile], e3 = col[(k + 3) * kListTile];
+            const uint32_t j0 = slot(e0), j1 = slot(e1), j2 = slot(e2), j3 = slot(e3);
+            const R r0 = pos[j0], r1 = pos[j1], r2 = pos[j2], r3 = pos[j3];
+            const auto p0 = load(j0), p1 = load(j1), p2 = load(j2), p3 = load(j3);
+            f(j0, r0, p0, Code::geom(ri, r0, e0 & Code::kMask, C));
+            f(j1, r1, p1, Code::geom(ri, r1, e1 & Code::kMask, C));
+            f(j2, r2, p2, Code::geom(ri, r2, e2 & Code::kMask, C));
+            f(j3, r3, p3, Code::geom(ri, r3, e3 & Code::kMask, C));
+        }
+        for (; k < cnt; ++k) {
+            const uint32_t e = col[k * kListTile];
+            const uint32_t j = slot(e);
+            const R rj = pos[j];
+            f(j, rj, load(j), Code::geom(ri, rj, e & Code::kMask, C));
+        }
+        return;
+    }
+    walk_pairs<DIM, S, T>(G, C, skey[i], ri, pos, skey, cstart, cend, n, load,
+                          [&](uint32_t j, const R& rj, const auto& pj, const Geom<T>& g,
+                              uint32_t) { f(j, rj, pj, g); });
+}
+
 // Neighbour loop without payload: f(j, rec_j, geom).
 template <int DIM, int S, typename T, typename Fn>
-__device__ __forceinline__ void for_each_neighbor(const Grid& G, const PairConst<T>& C,
-                                                  uint32_t key, const typename Rec<T>::type& ri,
-                                                  const typename Rec<T>::type* __restrict__ pos,
-                                                  const uint32_t* __restrict__ skey,
-                                                  const uint32_t* __restrict__ cstart,
-                                                  const uint32_t* __restrict__ cend, uint32_t n,
-                                                  Fn&& f) {
-    for_each_neighbor_p<DIM, S, T>(G, C, key, ri, pos, skey, cstart, cend, n, NoPayload(),
+__device__ __forceinline__ void for_each_neighbor(
+    int i, const Grid& G, const PairConst<T>& C, const typename Rec<T>::type& ri,
+    const typename Rec<T>::type* __restrict__ pos, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, uint32_t n,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap, Fn&& f) {
+    for_each_neighbor_p<DIM, S, T>(i, G, C, ri, pos, skey, cstart, cend, n, list, ncnt, cap,
+                                   NoPayload(),
                                    [&](uint32_t j, const typename Rec<T>::type& rj, int,
                                        const Geom<T>& g) { f(j, rj, g); });
 }
@@ -808,51 +909,294 @@ __device__ __forceinline__ void finish_density(int i, double rho, const PairCons
     }
 }
 
+// Uniform copies of lane t's values (t the same on every lane).
+__device__ __forceinline__ int lane_bcast(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+__device__ __forceinline__ double lane_bcast(double v, int t) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), t);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), t);
+    return __hiloint2double(hi, lo);
+}
+template <int DIM>
+__device__ __forceinline__ int4 rec_bcast(const int4& r, int t) {
+    int4 o;
+    o.x = lane_bcast(r.x, t);
+    o.y = lane_bcast(r.y, t);
+    o.z = DIM == 3 ? lane_bcast(r.z, t) : 0;
+    o.w = 0;
+    return o;
+}
+template <int DIM>
+__device__ __forceinline__ double4 rec_bcast(const double4& r, int t) {
+    double4 o;
+    o.x = lane_bcast(r.x, t);
+    o.y = lane_bcast(r.y, t);
+    o.z = DIM == 3 ? lane_bcast(r.z, t) : 0.0;
+    o.w = 0.0;
+    return o;
+}
+
+// Coordinates of the list builder's filter test, in FP32, relative to the
+// centre of the target cell c: the target's position, and the position of
+// candidate j's image for stencil offset o / periodic image w.  Their
+// difference is r_ij to within ~1e-6 of a cell (conversion and subtraction
+// roundings), well inside the +-1e-5 band of (2h)^2 around which the exact
+// FP64 predicate decides.
+__device__ __forceinline__ float filt_target(const int4& r, int k, const PairConst<float>& C,
+                                             double) {
+    return (float)(k == 0 ? r.x : (k == 1 ? r.y : r.z)) * C.fix_scale_f[k];
+}
+__device__ __forceinline__ float filt_cand(const int4& r, int k, int o, int,
+                                           const PairConst<float>& C, double) {
+    const int v = (k == 0 ? r.x : (k == 1 ? r.y : r.z)) + o * (1 << kFixBits);
+    return (float)v * C.fix_scale_f[k];
+}
+__device__ __forceinline__ float filt_target(const double4& r, int k, const PairConst<double>&,
+                                             double centre) {
+    return (float)((k == 0 ? r.x : (k == 1 ? r.y : r.z)) - centre);
+}
+__device__ __forceinline__ float filt_cand(const double4& r, int k, int, int w,
+                                           const PairConst<double>& C, double centre) {
+    const double v = k == 0 ? r.x : (k == 1 ? r.y : r.z);
+    return (float)((v + (w == 0 ? 0.0 : (w < 0 ? -C.L[k] : C.L[k]))) - centre);
+}
+
+// Neighbour lists of all particles (Sec. 2.2), built cell by cell: one wave
+// per cell (cells_per_wave consecutive cells per wave on very large grids).
+//  * Lane s < number of stencil segments (z row, y row, x piece) loads the
+//    slot range of segment s, and lane t the record of the cell's target t,
+//    all in one round of loads; the loops below read them with readlane.
+//  * The lanes take the candidates of the non-empty segments 64 at a time,
+//    in walk order (segments in order, ascending slots), with coalesced loads
+//    of their records, and test each candidate against every target in
+//    turn: an FP32 filter on cell-relative coordinates decides outside a
+//    band of +-1e-5 around (2h)^2, the exact FP64 predicate of walk_pairs
+//    inside it (and for coordinates too far from the cell for the filter's
+//    error bound), so the accepted set is exactly the walk's.  A ballot over
+//    the lanes hands each target its accepted candidates in walk order,
+//    appended to its list with one store.
+// So every candidate record is loaded once per cell instead of once per
+// target, and the lists are those of walk_pairs, entry for entry.  Entries
+// beyond cap are not stored; ncnt[i] holds the full count, and a count above
+// cap tells the pair kernels to walk the cells for that particle.  With
+// count_pairs, the number of interactions |N(i)| is added to the block's own
+// 64-bit counter pairs[block]: each block owns its slot (plain
+// read-modify-write, no atomics; launches are stream-ordered), and block 0
+// records the number of counters in pairs[-1] so that the reader can sum
+// them.
+template <int DIM, int SR, typename T>
+__global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32_t cells_per_wave,
+                                                  Grid G, PairConst<T> C,
+                                                  const uint32_t* __restrict__ skey,
+                                                  const typename Rec<T>::type* __restrict__ pos,
+                                                  const uint32_t* __restrict__ cstart,
+                                                  const uint32_t* __restrict__ cend, uint32_t cap,
+                                                  uint32_t* __restrict__ list,
+                                                  uint32_t* __restrict__ ncnt, int count_pairs,
+                                                  unsigned long long* __restrict__ pairs) {
+    using R = typename Rec<T>::type;
+    using Code = NbrCode<DIM, SR, T>;
+    constexpr bool kFp64 = sizeof(T) == 8;
+    constexpr int NR = 2 * SR + 1;
+    constexpr int kSegs = (DIM == 3 ? NR : 1) * NR * 2;
+    static_assert(kSegs <= 64, "one lane per stencil segment");
+    const int lane = (int)(threadIdx.x & 63);
+    const int blk = xcd_block();
+    const uint64_t wave = (uint64_t)blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t c0 = wave * cells_per_wave;
+    const uint64_t c1 = c0 + cells_per_wave < ncells ? c0 + cells_per_wave : ncells;
+    // stencil position of lane s's segment
+    const int sk = lane & 1, syi = (lane >> 1) % NR, szi = (lane >> 1) / NR;
+    const int soy = syi - SR, soz = DIM == 3 ? szi - SR : 0;
+    // FP64 records far from the cell (outside the box) take the exact test
+    const float far = (float)(4.0 * (G.cs[0] + G.cs[1] + G.cs[2]));
+    // Slot ranges of cell c (tb, te: the targets; lane s: segment s) and the
+    // segments' packed stencil data (oy, oz, wx, wy, wz as 3-bit fields, the
+    // code base above them) and x offset terms.  The loads of the next cell
+    // are issued before the current one is processed.
+    struct Ranges {
+        uint32_t tb, te, sb, se;
+        int meta, xoff;
+    };
+    auto load_ranges = [&](uint32_t c, Ranges& Rg) {
+        int cc[3];
+        decode_key(c, G, cc);
+        int first[2], last[2], wrap[2];
+        row_pieces<SR>(cc[0], G, first, last, wrap);
+        int cz = 0, wz = 0, cy = 0, wy = 0;
+        bool ok = lane < kSegs;
+        if (DIM == 3) ok = ok && stencil_axis(cc[2], soz, G.nc[2], G.periodic[2], &cz, &wz);
+        ok = ok && stencil_axis(cc[1], soy, G.nc[1], G.periodic[1], &cy, &wy);
+        const int fk = sk ? first[1] : first[0], lk = sk ? last[1] : last[0];
+        ok = ok && fk <= lk;
+        const int wx = sk ? wrap[1] : wrap[0];
+        const uint32_t row = (uint32_t)G.nc[0] * ((uint32_t)cy + (uint32_t)G.nc[1] * (uint32_t)cz);
+        Rg.sb = 0;
+        Rg.se = 0;
+        if (ok) {
+            Rg.sb = cstart[row + (uint32_t)fk];
+            Rg.se = cend[row + (uint32_t)lk];
+        }
+        Rg.tb = cstart[c];
+        Rg.te = cend[c];
+        Rg.xoff = wx * G.nc[0] - (int)row - cc[0];
+        Rg.meta = (soy + 2) | ((soz + 2) << 3) | ((wx + 2) << 6) | ((wy + 2) << 9) |
+                  ((wz + 2) << 12) | (Code::row_base(soy, soz, wx, wy, wz) << 15);
+    };
+    uint32_t total = 0;
+    Ranges cur{}, nxt{};
+    if (c0 < c1) load_ranges((uint32_t)c0, cur);
+    for (uint64_t cu = c0; cu < c1; ++cu) {
+        const uint32_t c = (uint32_t)cu;
+        if (cu + 1 < c1) load_ranges(c + 1, nxt);
+        const uint32_t tb = __builtin_amdgcn_readfirstlane(cur.tb);
+        uint32_t te = __builtin_amdgcn_readfirstlane(cur.te);
+        te = te < (uint32_t)n ? te : (uint32_t)n;
+        const uint32_t sb = cur.sb, se = cur.se < (uint32_t)n ? cur.se : (uint32_t)n;
+        const int smeta = cur.meta, sxoff = cur.xoff;
+        cur = nxt;
+        if (tb >= te) continue;
+        int cc[3];
+        decode_key(c, G, cc);
+        double centre[3];
+        for (int k = 0; k < 3; ++k) centre[k] = G.lo[k] + ((double)cc[k] + 0.5) * G.cs[k];
+        const unsigned long long segs = __ballot(sb < se);  // non-empty segments
+        for (uint32_t g0 = tb; g0 < te; g0 += 64) {  // targets, 64 at a time
+            const uint32_t nt = te - g0 < 64u ? te - g0 : 64u;
+            const R tr = pos[g0 + ((uint32_t)lane < nt ? (uint32_t)lane : 0u)];
+            float tf[3];
+            bool tfar = false;
+            for (int k = 0; k < DIM; ++k) {
+                tf[k] = filt_target(tr, k, C, centre[k]);
+                tfar |= kFp64 && !(fabsf(tf[k]) < far);
+            }
+            // with a far target in the group, every pair takes the exact test
+            const bool gfar = kFp64 && __ballot(tfar && (uint32_t)lane < nt) != 0ull;
+            uint32_t cntv = 0;  // lane t: count of target g0 + t
+            // this lane's candidate in the current chunk and its stencil data
+            uint32_t cj = 0;
+            int valid = 0, cmeta = 0, cxoff = 0;
+            uint32_t fill = 0;
+            auto process = [&]() {
+                const R rj = pos[cj];
+                const int ox = kFp64 ? 0 : (int)skey[cj] + cxoff;
+                const int oy = (cmeta & 7) - 2, oz = ((cmeta >> 3) & 7) - 2;
+                const int wx = ((cmeta >> 6) & 7) - 2, wy = ((cmeta >> 9) & 7) - 2;
+                const int wz = ((cmeta >> 12) & 7) - 2;
+                const uint32_t word = (cj << Code::kBits) | Code::code(cmeta >> 15, ox);
+                const int o[3] = {ox, oy, oz}, w[3] = {wx, wy, wz};
+                float cf[3];
+                bool cfar = false;
+                for (int k = 0; k < DIM; ++k) {
+                    cf[k] = filt_cand(rj, k, o[k], w[k], C, centre[k]);
+                    cfar |= kFp64 && !(fabsf(cf[k]) < far);
+                }
+                const bool exact_all = valid && (cfar || gfar);
+#pragma unroll 2
+                for (uint32_t t = 0; t < nt; ++t) {
+                    auto tcoord = [&](int k) {
+                        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tf[k]), t));
+                    };
+                    const float dx = tcoord(0) - cf[0], dy = tcoord(1) - cf[1];
+                    float r2 = dx * dx + dy * dy;
+                    if (DIM == 3) {
+                        const float dz = tcoord(2) - cf[2];
+                        r2 += dz * dz;
+                    }
+                    // accepted lanes: below the band, or inside it (or far) and
+                    // accepted by the exact predicate
+                    bool acc = valid && r2 < C.R2_lo;
+                    const bool band = exact_all || (valid && !(r2 < C.R2_lo) && r2 < C.R2_hi);
+                    if (__builtin_amdgcn_ballot_w64(band)) {
+                        const R ri = rec_bcast<DIM>(tr, (int)t);
+                        const Geom<T> gm = pair_geom<DIM>(ri, rj, ox, oy, oz, wx, wy, wz, C);
+                        acc = acc || (band && geom_r2d(gm, C) < C.R2_d);
+                    }
+                    const unsigned long long m = __builtin_amdgcn_ballot_w64(acc);
+                    const uint32_t base = __builtin_amdgcn_readlane(cntv, t);
+                    if (acc) {
+                        const uint32_t k = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
+                        // entry k of slot u = g0 + t: list + u + 64 (k + (u / 64)(cap - 1))
+                        const uint32_t u = g0 + t;
+                        uint32_t* __restrict__ lt =
+                            list + u + (size_t)(u / kListTile) * (size_t)(cap - 1) * kListTile;
+                        if (k < cap) lt[k * kListTile] = word;
+                    }
+                    if ((uint32_t)lane == t) cntv = base + (uint32_t)__popcll(m);
+                }
+                valid = 0;
+                fill = 0;
+            };
+            for (unsigned long long rest = segs; rest; rest &= rest - 1ull) {
+                const int seg = __ffsll((long long)rest) - 1;
+                uint32_t b = __builtin_amdgcn_readlane(sb, seg);
+                const uint32_t e = __builtin_amdgcn_readlane(se, seg);
+                const int meta = __builtin_amdgcn_readlane(smeta, seg);
+                const int xoff = __builtin_amdgcn_readlane(sxoff, seg);
+                while (b < e) {
+                    const uint32_t take = e - b < 64u - fill ? e - b : 64u - fill;
+                    if ((uint32_t)lane >= fill && (uint32_t)lane < fill + take) {
+                        cj = b + ((uint32_t)lane - fill);
+                        valid = 1;
+                        cmeta = meta;
+                        cxoff = xoff;
+                    }
+                    fill += take;
+                    b += take;
+                    if (fill == 64u) process();
+                }
+            }
+            if (fill) process();
+            if ((uint32_t)lane < nt) {
+                ncnt[g0 + (uint32_t)lane] = cntv;
+                total += cntv;
+            }
+        }
+    }
+    if (!count_pairs) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) total += __shfl_xor(total, d, 64);
+    __shared__ uint32_t wcnt[kBlock / 64];
+    if (lane == 0) wcnt[threadIdx.x >> 6] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
+        pairs[blk] += t;
+        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
+    }
+}
+
 // Summation density (eq. 2) and, if with_eos, the Tait EOS (eq. eos) with
-// P = p / rho^2 packed for the momentum pass.  Also adds the number of
-// interactions |N(i)| (self included) to the block's own 64-bit counter
-// pairs[block]: each block owns its slot (plain read-modify-write, no
-// atomics; launches are stream-ordered), and block 0 records the number of
-// counters in pairs[-1] so that the reader can sum them.
+// P = p / rho^2 packed for the momentum pass, over the neighbour lists.
 template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
                                                     const uint32_t* __restrict__ skey,
                                                     const typename Rec<T>::type* __restrict__ pos,
                                                     const uint32_t* __restrict__ cstart,
                                                     const uint32_t* __restrict__ cend,
-                                                    T* __restrict__ rho_out, T* __restrict__ p_out,
+                                                    const uint32_t* __restrict__ list,
+                                                    const uint32_t* __restrict__ ncnt,
+                                                    uint32_t cap, T* __restrict__ rho_out,
+                                                    T* __restrict__ p_out,
                                                     typename Vec2<T>::type* __restrict__ rp,
-                                                    int with_eos,
-                                                    unsigned long long* __restrict__ pairs) {
+                                                    int with_eos) {
     const int i = xcd_block() * kBlock + threadIdx.x;
-    uint32_t cnt = 0;
-    if (i < n) {
-        const typename Rec<T>::type ri = pos[i];
-        // The density terms are FP64 in both precisions: the EOS multiplies
-        // density rounding by ~7 B / rho0 before it reaches the forces.
-        double acc = 0.0;
-        for_each_neighbor<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
-                                  [&](uint32_t j, const typename Rec<T>::type& rj,
+    if (i >= n) return;
+    const typename Rec<T>::type ri = pos[i];
+    // The density terms are FP64 in both precisions: the EOS multiplies
+    // density rounding by ~7 B / rho0 before it reaches the forces.
+    double acc = 0.0;
+    for_each_neighbor<DIM, SR, T>(i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt,
+                                  cap,
+                                  [&](uint32_t, const typename Rec<T>::type& rj,
                                       const Geom<T>& g) {
-                                      const double q = density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
+                                      const double q =
+                                          density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
                                       acc += (double)rec_mass(rj) *
                                              kernel_w<KERNEL, double>(q, C.sigma_d);
-                                      ++cnt;
                                   });
-        finish_density<T>(i, acc, C, rho_out, p_out, rp, with_eos);
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
-    __shared__ uint32_t wcnt[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
-        const int blk = xcd_block();
-        pairs[blk] += t;
-        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
-    }
+    finish_density<T>(i, acc, C, rho_out, p_out, rp, with_eos);
 }
 
 // Momentum equation for fluid particles (walls: a = 0):
@@ -868,7 +1212,9 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
     const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
     const typename Vec2<T>::type* __restrict__ rp, const uint8_t* __restrict__ type,
-    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, State S, int kick,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap, State S,
+    int kick,
     int drift, double hdt, double dt, uint32_t* __restrict__ key, uint32_t* __restrict__ counts,
     uint32_t* __restrict__ flags, double* __restrict__ diag_part) {
     const int blk = xcd_block();
@@ -888,7 +1234,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
                 typename Vec2<T>::type rp;
             };
             for_each_neighbor_p<DIM, SR, T>(
-                G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
+                i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
                 [&](uint32_t j) { return Pay{vel[j], rp[j]}; },
                 [&](uint32_t j, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
                     if (j == (uint32_t)i) return;
@@ -947,8 +1293,9 @@ __global__ __launch_bounds__(kBlock) void k_nbr_count(int n, Grid G, PairConst<T
     if (i >= n) return;
     const typename Rec<T>::type ri = pos[i];
     uint32_t c = 0;
-    for_each_neighbor<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
-                              [&](uint32_t, const typename Rec<T>::type&, const Geom<T>&) { ++c; });
+    for_each_neighbor<DIM, SR, T>(i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, nullptr,
+                                  nullptr, 0u,
+                                  [&](uint32_t, const typename Rec<T>::type&, const Geom<T>&) { ++c; });
     cnt[i] = c;
 }
 
@@ -965,10 +1312,11 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill(int n, Grid G, PairConst<T>
     const typename Rec<T>::type ri = pos[i];
     int64_t w = off[i];
     const int64_t wend = off[i + 1];
-    for_each_neighbor<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
-                              [&](uint32_t j, const typename Rec<T>::type&, const Geom<T>&) {
-                                  if (w < wend) nbr[w++] = (int32_t)j;
-                              });
+    for_each_neighbor<DIM, SR, T>(i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, nullptr,
+                                  nullptr, 0u,
+                                  [&](uint32_t j, const typename Rec<T>::type&, const Geom<T>&) {
+                                      if (w < wend) nbr[w++] = (int32_t)j;
+                                  });
 }
 
 // Tait EOS alone (sph_eos).

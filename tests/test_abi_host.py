@@ -60,10 +60,24 @@ def test_grid_and_workspace_queries():
     assert sph.grid(prm2)[0] == (24, 24, 1)
 
 
+def test_workspace_holds_the_neighbour_lists():
+    """Lists take 4 bytes per entry, capacity (rounded up to a multiple of 4)
+    entries per particle in tiles of 64 particles; nbr_cap < 0 (cell walks
+    only) drops them."""
+    p, _ = W.taylor_green(32)
+    n = 1000  # 16 tiles of 64
+    walk = sph.workspace_bytes(sph.make_params(p, sph.FP64, -1), n)
+    for cap, rounded in ((8, 8), (62, 64), (100, 100), (1, 4)):
+        b = sph.workspace_bytes(sph.make_params(p, sph.FP64, cap), n)
+        assert 4 * rounded * 16 * 64 <= b - walk < 4 * rounded * 16 * 64 + 512  # + alignment
+    assert (sph.workspace_bytes(sph.make_params(p, sph.FP64, 0), n)
+            == sph.workspace_bytes(sph.make_params(p, sph.FP64, 64), n))
+
+
 @pytest.mark.parametrize("field,value", [("dim", 4), ("kernel", 7), ("precision", 3),
                                          ("cell_div", 3), ("h", 0.0), ("h", -1.0),
                                          ("rho0", 0.0), ("c0", 0.0), ("nu", -1.0),
-                                         ("eta", -0.5), ("reserved", 1)])
+                                         ("eta", -0.5), ("nbr_cap", 5000)])
 def test_invalid_params_rejected(field, value):
     prm = _params()
     setattr(prm, field, value)

@@ -13,19 +13,21 @@ from paper_1909_04504_amd.autograd import rollout_ke
 pytestmark = pytest.mark.gpu
 
 
-def _grads(p, s, nsteps, k, prec):
+def _grads(p, s, nsteps, k, prec, nbr_cap=0):
     u0 = torch.tensor(s.u, dtype=torch.float64, device="cuda", requires_grad=True)
     nu = torch.tensor(p.nu, dtype=torch.float64, requires_grad=True)
-    ke = rollout_ke(u0, nu, p, s.x, s.m, s.ptype, nsteps, k, prec)
+    ke = rollout_ke(u0, nu, p, s.x, s.m, s.ptype, nsteps, k, prec, nbr_cap)
     ke.backward()
     return float(ke), u0.grad.cpu().numpy(), float(nu.grad)
 
 
-@pytest.mark.parametrize("k", [1, 3, 8])
-def test_rollout_gradient_fp64_matches_oracle(k):
+@pytest.mark.parametrize("k,nbr_cap", [(1, 0), (3, 0), (8, 0), (3, -1), (3, 12)])
+def test_rollout_gradient_fp64_matches_oracle(k, nbr_cap):
+    """nbr_cap: default lists, cell walks only, and lists too short for most
+    particles (walked) beside ones that fit."""
     p, s = W.taylor_green(16, jitter=0.25, seed=3)
     nsteps = 8
-    ke, gu, gnu = _grads(p, s, nsteps, k, sph.FP64)
+    ke, gu, gnu = _grads(p, s, nsteps, k, sph.FP64, nbr_cap)
     gu_ref, gnu_ref, ke_ref = oracle.adjoint_ke(p, s.x, s.u, s.m, s.ptype, nsteps)
     assert ke == pytest.approx(ke_ref, rel=1e-12)
     assert normwise(gu, gu_ref) < 1e-10
@@ -105,8 +107,9 @@ def test_accel_backward_matches_oracle_transpose():
     p, s = W.periodic_cube(n_side=10, jitter=0.3, sigma_u=0.1, seed=5)
     rng = np.random.default_rng(1)
     lam = rng.standard_normal(s.x.shape)
-    for prec, tol in ((sph.FP64, 1e-11), (sph.FP32_MIXED, 2e-4)):
-        prm = sph.make_params(p, prec)
+    for prec, tol, cap in ((sph.FP64, 1e-11, 0), (sph.FP32_MIXED, 2e-4, 0),
+                           (sph.FP64, 1e-11, -1), (sph.FP32_MIXED, 2e-4, 40)):
+        prm = sph.make_params(p, prec, cap)
         dp = sph.DeviceParticles.from_state(s, prec)
         ws = sph.workspace(prm, s.n, adjoint_k=1)
         la = torch.tensor(lam, dtype=torch.float64, device="cuda")

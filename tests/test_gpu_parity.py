@@ -180,6 +180,45 @@ def test_taylor_green_64_trajectory_fp64():
     sph.check(ws)
 
 
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("prec", PRECS)
+def test_neighbour_list_capacity_paths(case, prec):
+    """The pair passes read each particle's neighbours from its list when it
+    fits the capacity and walk the cells otherwise: lists everywhere (default
+    capacity), walks everywhere (no lists) and a capacity that splits the
+    particles between the two give the same fields, and match the oracle."""
+    p, s = make_case(case)
+    s = drop_near_ties(p, s, 1e-5)
+    s = shuffled(s, 5)
+    ro, _ = oracle.neighbors(p, s.x, brute=False)
+    counts = np.diff(ro)
+    split = int(np.median(counts))  # about half the particles above it
+    outs = []
+    for cap in (0, -1, split):
+        prm = sph.make_params(p, prec, cap)
+        dp = sph.DeviceParticles.from_state(s, prec)
+        ws = sph.workspace(prm, s.n)
+        sph.step(prm, dp, 2, ws, prime=True)
+        sph.check(ws)
+        outs.append(dp.numpy())
+    ref = outs[0]
+    for o in outs[1:]:
+        for f in ("x", "u", "a", "rho", "p", "id"):
+            assert np.array_equal(o[f], ref[f]), f
+    # one more evaluation at the final state against the oracle
+    rho, _, a = oracle.evaluate(p, ref["x"], ref["u"], ref["m"], ref["type"])
+    prm = sph.make_params(p, prec, split)
+    dp = sph.DeviceParticles.from_state(W.State(ref["x"], ref["u"], ref["m"], ref["type"],
+                                                ref["id"]), prec)
+    ws = sph.workspace(prm, s.n)
+    sph.step(prm, dp, 0, ws, prime=True)
+    out = dp.numpy()
+    o = order_by_id(out["id"])
+    r = order_by_id(ref["id"])
+    assert normwise(out["rho"][o], rho[r]) < TOL_RHO[prec]
+    assert normwise(out["a"][:, o], a[:, r]) < TOL_ACC[prec]
+
+
 @pytest.mark.parametrize("case", ["tg2d", "cube3d", "dam3d"])
 def test_mixed_precision_few_steps(case):
     p, s = make_case(case)
