@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/sph.h: argument validation,
 // workspace layout and the launch sequences of every entry point.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdarg>
@@ -96,24 +97,24 @@ struct Timer {
 };
 Timer g_timer;
 
-// Brackets one launch with events on the launch stream while timing is on.
-struct Timed {
-    int id;
-    hipStream_t st;
-    hipEvent_t a = nullptr, b = nullptr;
-    Timed(int id_, hipStream_t st_) : id(id_), st(st_) {
-        if (!g_timer.on) return;
-        a = g_timer.get();
-        b = g_timer.get();
-        if (a && b) (void)hipEventRecord(a, st);
+// Launches kernel k on stream st with grid blocks of kBlock threads.  While
+// timing is on, the launch carries start and stop events recorded by the
+// dispatch itself (hipExtLaunchKernel), so the elapsed time is the kernel's
+// own duration.
+template <typename... KArgs, typename... Args>
+void launch(int id, void (*k)(KArgs...), unsigned grid, hipStream_t st, Args... args) {
+    if (g_timer.on) {
+        hipEvent_t a = g_timer.get(), b = g_timer.get();
+        if (a && b) {
+            hipExtLaunchKernelGGL(k, dim3(grid), dim3(sph::kBlock), 0, st, a, b, 0,
+                                  static_cast<KArgs>(args)...);
+            g_timer.pending.push_back({id, a, b});
+            if (g_timer.pending.size() > 200000) g_timer.fold();
+            return;
+        }
     }
-    ~Timed() {
-        if (!g_timer.on || !a || !b) return;
-        (void)hipEventRecord(b, st);
-        g_timer.pending.push_back({id, a, b});
-        if (g_timer.pending.size() > 200000) g_timer.fold();
-    }
-};
+    hipLaunchKernelGGL(k, dim3(grid), dim3(sph::kBlock), 0, st, static_cast<KArgs>(args)...);
+}
 
 // ---------------------------------------------------------------------------
 // Validation
@@ -479,8 +480,7 @@ struct Engine {
     }
 
     int zero_counts() {
-        Timed t_(K_FILL, st);
-        sph::k_fill_u32<<<blocks_for(ncells), sph::kBlock, 0, st>>>(ncells, 0u, counts());
+        launch(K_FILL, sph::k_fill_u32, blocks_for(ncells), st, ncells, 0u, counts());
         return launch_check("k_fill_u32");
     }
 
@@ -489,12 +489,10 @@ struct Engine {
     int scan(const uint32_t* in, int64_t len, OUT* out) {
         const unsigned nch = (unsigned)((len + sph::kScanChunk - 1) / sph::kScanChunk);
         {
-        Timed t_(K_CHUNK_SUM, st);
-        sph::k_chunk_sum<<<nch, sph::kBlock, 0, st>>>(in, len, chunks());
+        launch(K_CHUNK_SUM, sph::k_chunk_sum, nch, st, in, len, chunks());
         SPH_TRY(launch_check("k_chunk_sum"));
         }
-        Timed t_(K_CHUNK_SCAN, st);
-        sph::k_chunk_scan<OUT><<<nch, sph::kBlock, 0, st>>>(in, len, chunks(), out);
+        launch(K_CHUNK_SCAN, sph::k_chunk_scan<OUT>, nch, st, in, len, chunks(), out);
         return launch_check("k_chunk_scan");
     }
 
@@ -507,19 +505,16 @@ struct Engine {
         const unsigned nb = blocks_for(n);
         using TA = T;
         if (!hashed) {
-            Timed t_(K_HASH, st);
-            sph::k_drift_hash<DIM, TA><<<nb, sph::kBlock, 0, st>>>(
+            launch(K_HASH, sph::k_drift_hash<DIM, TA>, nb, st,
                 n, src, G, 0.5 * prm->dt, prm->dt, drift ? 1 : 0, key(), counts(), flags());
             SPH_TRY(launch_check("k_drift_hash"));
         }
         SPH_TRY(scan<uint32_t>(counts(), ncells, start()));
         {
-        Timed t_(K_SCATTER, st);
-        sph::k_scatter<<<nb, sph::kBlock, 0, st>>>(n, key(), start(), counts(), tmp());
+        launch(K_SCATTER, sph::k_scatter, nb, st, n, key(), start(), counts(), tmp());
         SPH_TRY(launch_check("k_scatter"));
         }
-        Timed t_(K_RANK_GATHER, st);
-        sph::k_rank_gather<DIM, T><<<nb, sph::kBlock, 0, st>>>(n, tmp(), key(), start(), src, dst, G,
+        launch(K_RANK_GATHER, sph::k_rank_gather<DIM, T>, nb, st, n, tmp(), key(), start(), src, dst, G,
                                                              perm(), skey(), pos(), vel(),
                                                              copy_derived ? 1 : 0, typetape);
         return launch_check("k_rank_gather");
@@ -532,9 +527,8 @@ struct Engine {
         unsigned nb;
         uint32_t cpw;
         nlist_grid(ncells, &nb, &cpw);
-        Timed t_(K_NLIST, st);
         with_reach([&](auto R) {
-            sph::k_nlist<DIM, decltype(R)::value, T><<<nb, sph::kBlock, 0, st>>>(
+            launch(K_NLIST, sph::k_nlist<DIM, decltype(R)::value, T>, nb, st,
                 n, (uint32_t)ncells, cpw, G, C, skey(), pos(), cs, ce, L.cap, list(), lcnt(),
                 count_pairs ? 1 : 0, pairs());
         });
@@ -545,9 +539,8 @@ struct Engine {
     // Lists of the current records, then the density over them.
     int density(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_eos) {
         SPH_TRY(nlist(cs, ce, true));
-        Timed t_(K_DENSITY, st);
         with_reach([&](auto R) {
-            sph::k_density<DIM, decltype(R)::value, KERNEL, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+            launch(K_DENSITY, sph::k_density<DIM, decltype(R)::value, KERNEL, T>, blocks_for(n), st,
                 n, G, C, skey(), pos(), cs, ce, list_or_null(), lcnt(), L.cap, (T*)s.rho,
                 (T*)s.p, rp(), with_eos ? 1 : 0);
         });
@@ -561,9 +554,8 @@ struct Engine {
         double* part = diag_out ? (double*)(ws + L.diag) : nullptr;
         const unsigned nb = blocks_for(n);
         {
-            Timed t_(K_MOMENTUM, st);
             with_reach([&](auto R) {
-                sph::k_momentum<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                launch(K_MOMENTUM, sph::k_momentum<DIM, decltype(R)::value, KERNEL, T>, nb, st,
                     n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, list_or_null(), lcnt(),
                     L.cap, s, kick ? 1 : 0,
                     drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(), flags(), part);
@@ -571,21 +563,18 @@ struct Engine {
             SPH_TRY(launch_check("k_momentum"));
         }
         if (!diag_out) return SPH_OK;
-        Timed t_(K_DIAG, st);
-        sph::k_diag_final<DIM><<<1, sph::kBlock, 0, st>>>((int)nb, part, diag_out);
+        launch(K_DIAG, sph::k_diag_final<DIM>, 1, st, (int)nb, part, diag_out);
         return launch_check("k_diag_final");
     }
 
     int pack(const sph::State& s, bool with_rp) {
-        Timed t_(K_PACK, st);
-        sph::k_pack<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, s, G, skey(), pos(), vel(),
+        launch(K_PACK, sph::k_pack<DIM, T>, blocks_for(n), st, n, s, G, skey(), pos(), vel(),
                                                                   rp(), with_rp ? 1 : 0);
         return launch_check("k_pack");
     }
 
     int copy(const sph::State& src, const sph::State& dst) {
-        Timed t_(K_COPY, st);
-        sph::k_copy_state<DIM, T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, src, dst);
+        launch(K_COPY, sph::k_copy_state<DIM, T>, blocks_for(n), st, n, src, dst);
         return launch_check("k_copy_state");
     }
 
@@ -597,8 +586,7 @@ struct Engine {
         SPH_TRY(zero_counts());
         SPH_TRY(sort_into(user, tmp_state, false, true));
         SPH_TRY(copy(tmp_state, user));
-        Timed t_(K_CELL_RANGES, st);
-        sph::k_cell_ranges<<<blocks_for(ncells), sph::kBlock, 0, st>>>(ncells, start(), cs_out, ce_out);
+        launch(K_CELL_RANGES, sph::k_cell_ranges, blocks_for(ncells), st, ncells, start(), cs_out, ce_out);
         return launch_check("k_cell_ranges");
     }
 
@@ -616,8 +604,7 @@ struct Engine {
     }
 
     int eos_only(sph_particles* pa) {
-        Timed t_(K_EOS, st);
-        sph::k_eos<T><<<blocks_for(n), sph::kBlock, 0, st>>>(n, C, (const T*)pa->rho, (T*)pa->p);
+        launch(K_EOS, sph::k_eos<T>, blocks_for(n), st, n, C, (const T*)pa->rho, (T*)pa->p);
         return launch_check("k_eos");
     }
 
@@ -626,9 +613,8 @@ struct Engine {
         const sph::State user = user_state(pa);
         SPH_TRY(pack(user, false));
         {
-        Timed t_(K_NBR_COUNT, st);
         with_reach([&](auto R) {
-            sph::k_nbr_count<DIM, decltype(R)::value, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+            launch(K_NBR_COUNT, sph::k_nbr_count<DIM, decltype(R)::value, T>, blocks_for(n), st,
                 n, G, C, skey(), pos(), cs, ce, ncnt());
         });
         SPH_TRY(launch_check("k_nbr_count"));
@@ -642,9 +628,8 @@ struct Engine {
             return fail(SPH_ECAPACITY, "neighbour list needs %lld entries, capacity %lld",
                         (long long)tot, (long long)capacity);
         if (tot > 0 && !nbr) return fail(SPH_EINVAL, "nbr is NULL");
-        Timed t_(K_NBR_FILL, st);
         with_reach([&](auto R) {
-            sph::k_nbr_fill<DIM, decltype(R)::value, T><<<blocks_for(n), sph::kBlock, 0, st>>>(
+            launch(K_NBR_FILL, sph::k_nbr_fill<DIM, decltype(R)::value, T>, blocks_for(n), st,
                 n, G, C, skey(), pos(), cs, ce, offsets, nbr);
         });
         return launch_check("k_nbr_fill");
@@ -691,33 +676,29 @@ struct Engine {
         double* nup = (double*)(ws + L.nupart);
         double* part = (double*)(ws + L.diag);
         {
-            Timed t_(K_ADJ_SEED, st);
-            sph::k_adj_seed<DIM, T><<<nb, sph::kBlock, 0, st>>>(n, lam_u, lam_a, ld, hdt, type,
+            launch(K_ADJ_SEED, sph::k_adj_seed<DIM, T>, nb, st, n, lam_u, lam_a, ld, hdt, type,
                                                                gather, lhat);
             SPH_TRY(launch_check("k_adj_seed"));
         }
         {
-            Timed t_(K_ADJ_PAIR1, st);
             with_reach([&](auto R) {
-                sph::k_adj_pair1<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                launch(K_ADJ_PAIR1, sph::k_adj_pair1<DIM, decltype(R)::value, KERNEL, T>, nb, st,
                     n, G, C, skey(), pos(), vel(), rp(), lhat, start(), start() + 1,
                     list_or_null(), lcnt(), L.cap, lxd, lvd, lrho, nup);
             });
             SPH_TRY(launch_check("k_adj_pair1"));
         }
         {
-            Timed t_(K_ADJ_PAIR2, st);
             with_reach([&](auto R) {
-                sph::k_adj_pair2<DIM, decltype(R)::value, KERNEL, T><<<nb, sph::kBlock, 0, st>>>(
+                launch(K_ADJ_PAIR2, sph::k_adj_pair2<DIM, decltype(R)::value, KERNEL, T>, nb, st,
                     n, G, C, skey(), pos(), lrho, start(), start() + 1, list_or_null(), lcnt(),
                     L.cap, lxd);
             });
             SPH_TRY(launch_check("k_adj_pair2"));
         }
-        Timed t_(K_ADJ_REDUCE, st);
-        sph::k_sum_partial<<<nb, sph::kBlock, 0, st>>>(n, nup, part);
+        launch(K_ADJ_REDUCE, sph::k_sum_partial, nb, st, n, nup, part);
         SPH_TRY(launch_check("k_sum_partial"));
-        sph::k_sum_accum<<<1, sph::kBlock, 0, st>>>((int)nb, part, dJ);
+        launch(K_ADJ_REDUCE, sph::k_sum_accum, 1, st, (int)nb, part, dJ);
         return launch_check("k_sum_accum");
     }
 
@@ -746,8 +727,7 @@ struct Engine {
             double* out = s == 0 ? lam_out : bufs[s & 1];
             SPH_TRY(adjoint_rhs(in + DIM * N, in + 2 * DIM * N, N, hdt, typetape, nullptr, dJ,
                                 true));
-            Timed t_(K_ADJ_KICK, st);
-            sph::k_adj_kick<DIM><<<blocks_for(n), sph::kBlock, 0, st>>>(
+            launch(K_ADJ_KICK, sph::k_adj_kick<DIM>, blocks_for(n), st,
                 n, in, (const double*)(ws + L.lxd), (const double*)(ws + L.lvd), typetape, perm(),
                 prm->dt, hdt, out);
             SPH_TRY(launch_check("k_adj_kick"));
@@ -767,8 +747,7 @@ struct Engine {
         SPH_TRY(sort_into(user, s1, false, false));
         SPH_TRY(density(s1, start(), start() + 1, true));
         SPH_TRY(adjoint_rhs(nullptr, lam_a, n, 0.0, s1.type, perm(), dJ, false));
-        Timed t_(K_ADJ_KICK, st);
-        sph::k_adj_accum<DIM><<<blocks_for(n), sph::kBlock, 0, st>>>(
+        launch(K_ADJ_KICK, sph::k_adj_accum<DIM>, blocks_for(n), st,
             n, (const double*)(ws + L.lxd), (const double*)(ws + L.lvd), s1.type, perm(), lam_x,
             lam_u);
         return launch_check("k_adj_accum");

@@ -1091,7 +1091,6 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
                     cfar |= kFp64 && !(fabsf(cf[k]) < far);
                 }
                 const bool exact_all = valid && (cfar || gfar);
-#pragma unroll 2
                 for (uint32_t t = 0; t < nt; ++t) {
                     auto tcoord = [&](int k) {
                         return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tf[k]), t));
