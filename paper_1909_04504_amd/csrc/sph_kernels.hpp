@@ -578,23 +578,50 @@ __device__ __forceinline__ void for_each_neighbor_p(
         const uint32_t* __restrict__ col = list + list_column((uint32_t)i, cap);
         // slot of entry e (clamped into [0, n), which a current list never needs)
         auto slot = [&](uint32_t e) { return min(e >> Code::kBits, n - 1u); };
+        // entry k, read within the particle's cap entries (values past cnt
+        // are loaded ahead but never used)
+        auto entry = [&](uint32_t k) { return col[min(k, cap - 1u) * kListTile]; };
+        // groups of kGroup neighbours: their records are gathered together,
+        // and the entries of the next group are loaded meanwhile
+        constexpr uint32_t kGroup = 4;
+        using P = decltype(load(0u));
+        uint32_t q[kGroup];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) q[u] = entry(u);
         uint32_t k = 0;
-        for (; k + 4 <= cnt; k += 4) {
-            const uint32_t e0 = col[(k + 0) * kListTile], e1 = col[(k + 1) * kListTile];
-            const uint32_t e2 = col[(k + 2) * kListTile], e3 = col[(k + 3) * kListTile];
-            const uint32_t j0 = slot(e0), j1 = slot(e1), j2 = slot(e2), j3 = slot(e3);
-            const R r0 = pos[j0], r1 = pos[j1], r2 = pos[j2], r3 = pos[j3];
-            const auto p0 = load(j0), p1 = load(j1), p2 = load(j2), p3 = load(j3);
-            f(j0, r0, p0, Code::geom(ri, r0, e0 & Code::kMask, C));
-            f(j1, r1, p1, Code::geom(ri, r1, e1 & Code::kMask, C));
-            f(j2, r2, p2, Code::geom(ri, r2, e2 & Code::kMask, C));
-            f(j3, r3, p3, Code::geom(ri, r3, e3 & Code::kMask, C));
+        for (; k + kGroup <= cnt; k += kGroup) {
+            uint32_t jj[kGroup], cc[kGroup];
+            R rr[kGroup];
+            P pp[kGroup];
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) {
+                jj[u] = slot(q[u]);
+                cc[u] = q[u] & Code::kMask;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) rr[u] = pos[jj[u]];
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) pp[u] = load(jj[u]);
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) q[u] = entry(k + kGroup + u);
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) f(jj[u], rr[u], pp[u], Code::geom(ri, rr[u], cc[u], C));
         }
-        for (; k < cnt; ++k) {
-            const uint32_t e = col[k * kListTile];
-            const uint32_t j = slot(e);
-            const R rj = pos[j];
-            f(j, rj, load(j), Code::geom(ri, rj, e & Code::kMask, C));
+        // fewer than kGroup entries left, already loaded: gathered together
+        // too (unused ones read slot i's own, cached, records)
+        {
+            uint32_t jj[kGroup - 1];
+            R rr[kGroup - 1];
+            P pp[kGroup - 1];
+#pragma unroll
+            for (uint32_t u = 0; u + 1 < kGroup; ++u) jj[u] = k + u < cnt ? slot(q[u]) : (uint32_t)i;
+#pragma unroll
+            for (uint32_t u = 0; u + 1 < kGroup; ++u) rr[u] = pos[jj[u]];
+#pragma unroll
+            for (uint32_t u = 0; u + 1 < kGroup; ++u) pp[u] = load(jj[u]);
+#pragma unroll
+            for (uint32_t u = 0; u + 1 < kGroup; ++u)
+                if (k + u < cnt) f(jj[u], rr[u], pp[u], Code::geom(ri, rr[u], q[u] & Code::kMask, C));
         }
         return;
     }
