@@ -1262,14 +1262,19 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
             for_each_neighbor_p<DIM, SR, T>(
                 i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
                 [&](uint32_t j) { return Pay{vel[j], rp[j]}; },
-                [&](uint32_t j, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
-                    if (j == (uint32_t)i) return;
+                [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
+                    // The self pair (j = i) is not skipped: r = 0 and
+                    // v_i - v_i = 0 multiply finite factors (F is finite at
+                    // r = 0 and the viscous factor is taken as 0 there), so
+                    // it adds exactly zero, without a branch in the loop.
                     const typename Vec4<T>::type vj = pj.v;
                     const typename Vec2<T>::type rpj = pj.rp;
                     const T r2 = g.r2;
                     const T F = kernel_f_r2<KERNEL, T>(r2, C);
                     const T pres = -(rpi.y + rpj.y) * F;
-                    const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
+                    const T visc = r2 > T(0) ? C.four_nu * F * r2 *
+                                                   p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2))
+                                             : T(0);
                     const T mj = rec_mass(rj);
                     ax += mj * (pres * g.d[0] + visc * (vi.x - vj.x));
                     ay += mj * (pres * g.d[1] + visc * (vi.y - vj.y));
