@@ -101,9 +101,9 @@ def traffic_from_profile(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def run_precision(sph, torch, wl, prec, steps, warmup, timing):
+def run_precision(sph, torch, wl, prec, steps, warmup, timing, nbr_cap=0):
     p, s = wl.params, wl.state
-    prm = sph.make_params(p, prec)
+    prm = sph.make_params(p, prec, nbr_cap)
     dp = sph.DeviceParticles.from_state(s, prec)
     ws = sph.workspace(prm, s.n)
     sph.step(prm, dp, 0, ws, prime=True)
@@ -288,6 +288,9 @@ def main():
     ap.add_argument("--workload", default="tg512")
     ap.add_argument("--cell-div", type=int, default=0,
                     help="cells per support radius (default: the workload's)")
+    ap.add_argument("--nbr-cap", type=int, default=0,
+                    help="neighbour-list capacity per particle (0: the library default, "
+                         "-1: no lists, every pair pass walks the cells)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -320,11 +323,13 @@ def main():
     if args.cell_div:
         wl.params = wl.params.replace(cell_div=args.cell_div)
     print(f"# workload {wl.name}: {wl.description}; n={wl.state.n}", file=sys.stderr, flush=True)
-    mixed = run_precision(sph, torch, wl, sph.FP32_MIXED, args.steps, args.warmup, True)
+    mixed = run_precision(sph, torch, wl, sph.FP32_MIXED, args.steps, args.warmup, True,
+                          args.nbr_cap)
     print(f"# fp32-mixed: {mixed['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_precision(sph, torch, wl, sph.FP64, args.steps, args.warmup, True)
+        fp64 = run_precision(sph, torch, wl, sph.FP64, args.steps, args.warmup, True,
+                             args.nbr_cap)
         print(f"# fp64: {fp64['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     rl = roofline(mixed, wl, sph.FP32_MIXED, args.steps, mixed["pair_tests"])
     adj = None
@@ -350,7 +355,8 @@ def main():
         "dtype": "f32 pair terms + f64 integration",
         "data": "synthetic (seeded jittered lattice, analytic Taylor-Green velocities)",
         "config": {"workload": wl.name, "description": wl.description, "particles": wl.state.n,
-                   "kernel": "cubic spline", "h_over_dx": 1.3, "rebuild": "every step"},
+                   "kernel": "cubic spline", "h_over_dx": 1.3, "rebuild": "every step",
+                   "nbr_cap": args.nbr_cap},
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": rl,
         "fp32_mixed": mixed,

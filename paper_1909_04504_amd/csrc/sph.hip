@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -282,11 +283,12 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
     const int64_t longest = (ncells + 1 > n + 1) ? ncells + 1 : n + 1;
     const size_t nchunks = (size_t)((longest + sph::kScanChunk - 1) / sph::kScanChunk);
     // header (flag word at 0, number of interaction counters at 8), then one
-    // 64-bit interaction counter per k_nlist block from offset 16
+    // 64-bit interaction counter per block of the counting kernel (k_nlist,
+    // or k_density without lists) from offset 16
     unsigned nl_blocks;
     uint32_t nl_cpw;
     nlist_grid(ncells, &nl_blocks, &nl_cpw);
-    L.flags = take(16 + 8 * (size_t)nl_blocks);
+    L.flags = take(16 + 8 * (size_t)std::max(nl_blocks, blocks_for(n)));
     L.counts = take(4 * (size_t)ncells);
     L.start = take(4 * ((size_t)ncells + 1));
     L.chunks = take(8 * nchunks);
@@ -524,25 +526,36 @@ struct Engine {
     // of interactions to the counters).  Every pair pass reads the lists
     // built last, so each change of records is followed by this launch.
     int nlist(const uint32_t* cs, const uint32_t* ce, bool count_pairs) {
-        unsigned nb;
-        uint32_t cpw;
-        nlist_grid(ncells, &nb, &cpw);
         with_reach([&](auto R) {
-            launch(K_NLIST, sph::k_nlist<DIM, decltype(R)::value, T>, nb, st,
-                n, (uint32_t)ncells, cpw, G, C, skey(), pos(), cs, ce, L.cap, list(), lcnt(),
-                count_pairs ? 1 : 0, pairs());
+            // cell-cooperative build in 2D with cells of 2h (about 7 targets
+            // and 61 candidates per cell); the walk build elsewhere, where a
+            // cell's candidates are many times a wave (measured: 3D dam break
+            // 0.88 ms walk at cell_div 2 against 2.6 ms cooperative at 1)
+            if (DIM == 2 && decltype(R)::value == 1) {
+                unsigned nb;
+                uint32_t cpw;
+                nlist_grid(ncells, &nb, &cpw);
+                launch(K_NLIST, sph::k_nlist<DIM, decltype(R)::value, T>, nb, st, n,
+                       (uint32_t)ncells, cpw, G, C, skey(), pos(), cs, ce, L.cap, list(), lcnt(),
+                       count_pairs ? 1 : 0, pairs());
+            } else {
+                launch(K_NLIST, sph::k_nlist_walk<DIM, decltype(R)::value, T>, blocks_for(n), st,
+                       n, G, C, skey(), pos(), cs, ce, L.cap, list(), lcnt(), count_pairs ? 1 : 0,
+                       pairs());
+            }
         });
         return launch_check("k_nlist");
     }
     const uint32_t* list_or_null() const { return L.cap ? list() : nullptr; }
 
-    // Lists of the current records, then the density over them.
+    // Lists of the current records, then the density over them; without
+    // lists the density walk counts the interactions.
     int density(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_eos) {
-        SPH_TRY(nlist(cs, ce, true));
+        if (L.cap) SPH_TRY(nlist(cs, ce, true));
         with_reach([&](auto R) {
             launch(K_DENSITY, sph::k_density<DIM, decltype(R)::value, KERNEL, T>, blocks_for(n), st,
                 n, G, C, skey(), pos(), cs, ce, list_or_null(), lcnt(), L.cap, (T*)s.rho,
-                (T*)s.p, rp(), with_eos ? 1 : 0);
+                (T*)s.p, rp(), with_eos ? 1 : 0, L.cap ? 0 : 1, pairs());
         });
         return launch_check("k_density");
     }
@@ -599,7 +612,7 @@ struct Engine {
     int momentum_only(sph_particles* pa, const uint32_t* cs, const uint32_t* ce) {
         const sph::State user = user_state(pa);
         SPH_TRY(pack(user, true));
-        SPH_TRY(nlist(cs, ce, false));
+        if (L.cap) SPH_TRY(nlist(cs, ce, false));
         return momentum(user, cs, ce, false);
     }
 
@@ -668,7 +681,7 @@ struct Engine {
     int adjoint_rhs(const double* lam_u, const double* lam_a, int64_t ld, double hdt,
                     const uint8_t* type, const uint32_t* gather, double* dJ, bool build_list) {
         const unsigned nb = blocks_for(n);
-        if (build_list) SPH_TRY(nlist(start(), start() + 1, false));
+        if (build_list && L.cap) SPH_TRY(nlist(start(), start() + 1, false));
         V4* lhat = (V4*)(ws + L.lhat);
         double* lxd = (double*)(ws + L.lxd);
         double* lvd = (double*)(ws + L.lvd);

@@ -1193,8 +1193,55 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
     }
 }
 
+// Neighbour lists of all particles (Sec. 2.2), one particle per lane: the
+// cell walk of walk_pairs, each accepted neighbour (self included) stored as
+// (j << bits) | code while the list has room; ncnt[i] = the full count.
+// Interaction counters as in k_nlist.
+template <int DIM, int SR, typename T>
+__global__ __launch_bounds__(kBlock) void k_nlist_walk(int n, Grid G, PairConst<T> C,
+                                                       const uint32_t* __restrict__ skey,
+                                                       const typename Rec<T>::type* __restrict__ pos,
+                                                       const uint32_t* __restrict__ cstart,
+                                                       const uint32_t* __restrict__ cend,
+                                                       uint32_t cap, uint32_t* __restrict__ list,
+                                                       uint32_t* __restrict__ ncnt, int count_pairs,
+                                                       unsigned long long* __restrict__ pairs) {
+    using R = typename Rec<T>::type;
+    const int blk = xcd_block();
+    const int i = blk * kBlock + threadIdx.x;
+    uint32_t cnt = 0;
+    if (i < n) {
+        const R ri = pos[i];
+        uint32_t* __restrict__ col = list + list_column((uint32_t)i, cap);
+        walk_pairs<DIM, SR, T>(G, C, skey[i], ri, pos, skey, cstart, cend, (uint32_t)n,
+                               NoPayload(),
+                               [&](uint32_t j, const R&, int, const Geom<T>&, uint32_t code) {
+                                   if (cnt < cap)
+                                       col[cnt * kListTile] =
+                                           (j << NbrCode<DIM, SR, T>::kBits) | code;
+                                   ++cnt;
+                               });
+        ncnt[i] = cnt;
+    }
+    if (!count_pairs) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    __shared__ uint32_t wcnt[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
+        pairs[blk] += t;
+        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
+    }
+}
+
 // Summation density (eq. 2) and, if with_eos, the Tait EOS (eq. eos) with
-// P = p / rho^2 packed for the momentum pass, over the neighbour lists.
+// P = p / rho^2 packed for the momentum pass, over the neighbour lists (or
+// the cell walk).  Without lists (list == nullptr) and with count_pairs, the
+// number of interactions |N(i)| is added to the block's own counter
+// pairs[block] as the list build does otherwise.
 template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
                                                     const uint32_t* __restrict__ skey,
@@ -1206,23 +1253,40 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
                                                     uint32_t cap, T* __restrict__ rho_out,
                                                     T* __restrict__ p_out,
                                                     typename Vec2<T>::type* __restrict__ rp,
-                                                    int with_eos) {
-    const int i = xcd_block() * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const typename Rec<T>::type ri = pos[i];
-    // The density terms are FP64 in both precisions: the EOS multiplies
-    // density rounding by ~7 B / rho0 before it reaches the forces.
-    double acc = 0.0;
-    for_each_neighbor<DIM, SR, T>(i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt,
-                                  cap,
-                                  [&](uint32_t, const typename Rec<T>::type& rj,
-                                      const Geom<T>& g) {
-                                      const double q =
-                                          density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
-                                      acc += (double)rec_mass(rj) *
-                                             kernel_w<KERNEL, double>(q, C.sigma_d);
-                                  });
-    finish_density<T>(i, acc, C, rho_out, p_out, rp, with_eos);
+                                                    int with_eos, int count_pairs,
+                                                    unsigned long long* __restrict__ pairs) {
+    const int blk = xcd_block();
+    const int i = blk * kBlock + threadIdx.x;
+    uint32_t cnt = 0;
+    if (i < n) {
+        const typename Rec<T>::type ri = pos[i];
+        // The density terms are FP64 in both precisions: the EOS multiplies
+        // density rounding by ~7 B / rho0 before it reaches the forces.
+        double acc = 0.0;
+        for_each_neighbor<DIM, SR, T>(i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list,
+                                      ncnt, cap,
+                                      [&](uint32_t, const typename Rec<T>::type& rj,
+                                          const Geom<T>& g) {
+                                          const double q =
+                                              density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
+                                          acc += (double)rec_mass(rj) *
+                                                 kernel_w<KERNEL, double>(q, C.sigma_d);
+                                          ++cnt;
+                                      });
+        finish_density<T>(i, acc, C, rho_out, p_out, rp, with_eos);
+    }
+    if (!count_pairs) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    __shared__ uint32_t wcnt[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
+        pairs[blk] += t;
+        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
+    }
 }
 
 // Momentum equation for fluid particles (walls: a = 0):

@@ -220,10 +220,12 @@ def workload(name: str, **kw) -> Workload:
         p, s = taylor_green(32, **kw)
         return Workload(name, p, s, 200, "fp64", "2D Taylor-Green 32x32 (adjoint companion)")
     if name == "dambreak3d":
+        kw.setdefault("cell_div", 2)
         p, s = dam_break_3d(**kw)
         return Workload(name, p, s, 500, "fp32",
                         "3D dam-break box, Wendland C2 h=1.3dx, gravity, 500 steps")
     if name == "cube256":
+        kw.setdefault("cell_div", 2)
         p, s = periodic_cube(**kw)
         return Workload(name, p, s, 1, "fp32",
                         "3D periodic cube 256^3 jittered +-0.2dx, Wendland C2 h=1.5dx, 1 step")
