@@ -383,7 +383,7 @@ __device__ __forceinline__ bool pair_accept(const Geom<float>& g, const PairCons
     bool acc = g.r2 < C.R2_lo;
     const bool band = !acc && g.r2 < C.R2_hi;
     // the FP64 test runs only when some lane of the wave is inside the band
-    if (__ballot(band)) acc = acc || (band && geom_r2d(g, C) < C.R2_d);
+    if (__builtin_amdgcn_ballot_w64(band)) acc = acc || (band && geom_r2d(g, C) < C.R2_d);
     return acc;
 }
 
@@ -534,25 +534,29 @@ __device__ __forceinline__ void walk_pairs(const Grid& G, const PairConst<T>& C,
                 const int wx = wrap[k];
                 const int xoff = wx * G.nc[0] - xbase;
                 const int cb = Code::row_base(oy, oz, wx, wy, wz);
-                auto ox_of = [&](uint32_t j) { return (int)skey[j] + xoff; };
                 auto visit = [&](uint32_t j, const R& rj, const auto& pj, int ox) {
                     const Geom<T> g = pair_geom<DIM>(ri, rj, ox, oy, oz, wx, wy, wz, C);
                     if (pair_accept(g, C)) f(j, rj, pj, g, Code::code(cb, ox));
                 };
                 const uint32_t e = pe[yi][k];
                 uint32_t j = pb[yi][k];
-                for (; j + 4 <= e; j += 4) {
-                    const R r0 = pos[j], r1 = pos[j + 1], r2 = pos[j + 2], r3 = pos[j + 3];
-                    const int o0 = ox_of(j), o1 = ox_of(j + 1), o2 = ox_of(j + 2), o3 = ox_of(j + 3);
+                // records and keys of the row through pointers, so that
+                // consecutive candidates are immediate offsets of one address
+                const R* __restrict__ pr = pos + j;
+                const uint32_t* __restrict__ pk = skey + j;
+                for (; j + 4 <= e; j += 4, pr += 4, pk += 4) {
+                    const R r0 = pr[0], r1 = pr[1], r2 = pr[2], r3 = pr[3];
+                    const int o0 = (int)pk[0] + xoff, o1 = (int)pk[1] + xoff;
+                    const int o2 = (int)pk[2] + xoff, o3 = (int)pk[3] + xoff;
                     const auto p0 = load(j), p1 = load(j + 1), p2 = load(j + 2), p3 = load(j + 3);
                     visit(j, r0, p0, o0);
                     visit(j + 1, r1, p1, o1);
                     visit(j + 2, r2, p2, o2);
                     visit(j + 3, r3, p3, o3);
                 }
-                for (; j < e; ++j) {
-                    const R rj = pos[j];
-                    const int oj = ox_of(j);
+                for (; j < e; ++j, ++pr, ++pk) {
+                    const R rj = pr[0];
+                    const int oj = (int)pk[0] + xoff;
                     const auto pj = load(j);
                     visit(j, rj, pj, oj);
                 }
