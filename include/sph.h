@@ -53,10 +53,18 @@ typedef enum {
 
 typedef enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 } sph_precision;
 
-/* Smoothing kernels with support radius R = 2h.  Cubic spline: the M4 spline
- * (Monaghan 1992), which PySPH names CubicSpline.  Wendland C2: Wendland
- * (1995), scaled to support 2h. */
-typedef enum { SPH_CUBIC_SPLINE = 0, SPH_WENDLAND_C2 = 1 } sph_kernel;
+/* Smoothing kernels W(|r|, h) = sigma_d w(|r|/h) (Section 2, compact
+ * support k h).  Cubic spline: the M4 spline (Monaghan 1992), which PySPH
+ * names CubicSpline, support 2h.  Wendland C2: Wendland (1995), scaled to
+ * support 2h.  Quintic spline: (3-q)^5 - 6 (2-q)_+^5 + 15 (1-q)_+^5 (Morris
+ * 1997), which PySPH names QuinticSpline, support 3h, sigma_2 = 7/(478 pi h^2),
+ * sigma_3 = 1/(120 pi h^3).  The support radius R sets the neighbour
+ * predicate |r| < R and the cell size (>= R / cell_div). */
+typedef enum {
+    SPH_CUBIC_SPLINE = 0,
+    SPH_WENDLAND_C2 = 1,
+    SPH_QUINTIC_SPLINE = 2
+} sph_kernel;
 
 typedef enum { SPH_FLUID = 0, SPH_WALL = 1 } sph_particle_type;
 
@@ -97,7 +105,7 @@ typedef struct {
     int32_t* id;     /* caller's ids; permuted with the particles */
 } sph_particles;
 
-/* Cell grid of `prm` (host only).  nc[k] = max(1, floor((hi-lo) cell_div / 2h))
+/* Cell grid of `prm` (host only).  nc[k] = max(1, floor((hi-lo) cell_div / R))
  * cells along axis k < dim (1 for unused axes), *ncells their product.
  * Returns SPH_EINVAL if a periodic axis has fewer than 2 cell_div + 1 cells
  * (a neighbour would be reached twice) or the grid exceeds 2^31 cells. */
@@ -120,7 +128,7 @@ int sph_bin_sort(const sph_params* prm, sph_particles* pa, void* ws, size_t ws_b
                  uint32_t* cell_start, uint32_t* cell_end, void* stream);
 
 /* Neighbour lists (Section 2.2) of particles sorted by sph_bin_sort with the
- * same parameters: j is a neighbour of i iff |x_i - x_j| < 2h, with the
+ * same parameters: j is a neighbour of i iff |x_i - x_j| < R, with the
  * minimum image on periodic axes, i itself included.  Written as CSR:
  * offsets[0..n] (int64) and nbr[offsets[i] .. offsets[i+1]) (sorted-order
  * indices).  Two phases: counts are formed and *total (host) is set; if

@@ -13,8 +13,8 @@
  *   - Everything is double precision; no fused or reordered arithmetic beyond
  *     what the definitions state (build with -ffp-contract=off).
  *   - Neighbour set (Section "Nearest neighbor particle search", A1, A13):
- *       j in N(i)  <=>  |x_i - x_j|^2 < (2h)^2, minimum image on periodic
- *       axes, i itself included.
+ *       j in N(i)  <=>  |x_i - x_j|^2 < R^2 (R = 2h; 3h for the quintic
+ *       spline), minimum image on periodic axes, i itself included.
  *     Computed by brute force O(n^2) or by the paper's uniform cell grid with
  *     the (2s+1)^d stencil; both give the same set (pinned by the tests).
  *
@@ -37,7 +37,7 @@ struct OrcParams {
     int32_t brute;       /* 1: brute-force neighbour sets; 0: cell list */
     int32_t periodic[3];
     int32_t pad_;
-    double h;            /* smoothing length; support radius R = 2h (A1) */
+    double h;            /* smoothing length; support radius R = 2h, 3h for the quintic (A1) */
     double rho0;         /* reference density */
     double c0;           /* reference speed of sound */
     double nu;           /* kinematic viscosity */
@@ -53,22 +53,50 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
-/* ---- Smoothing kernels (Section 2: compact W with support k h, k = 2) ---- */
+/* ---- Smoothing kernels (Section 2: compact W with support k h; k = 2 for
+ * the cubic spline and Wendland C2, k = 3 for the quintic spline) ---- */
 
-/* Normalisation sigma so that the integral of W over R^d is one (A2, A3). */
+/* Support radius R = k h. */
+double support(const OrcParams& P) { return (P.kernel == 2 ? 3.0 : 2.0) * P.h; }
+
+/* Normalisation sigma so that the integral of W over R^d is one (A2, A3, and
+ * for the quintic the exact integrals of its shape: 239 pi/7 in 2D and
+ * 120 pi in 3D, in units of h^d). */
 double sigma(const OrcParams& P) {
     const double h = P.h;
     if (P.kernel == 0) {  /* cubic spline (Monaghan 1992 M4) */
         return P.dim == 2 ? 10.0 / (7.0 * kPi * h * h) : 1.0 / (kPi * h * h * h);
     }
+    if (P.kernel == 2) {  /* quintic spline (Morris 1997), support 3h */
+        return P.dim == 2 ? 7.0 / (478.0 * kPi * h * h) : 1.0 / (120.0 * kPi * h * h * h);
+    }
     /* Wendland C2 scaled to support 2h */
     return P.dim == 2 ? 7.0 / (4.0 * kPi * h * h) : 21.0 / (16.0 * kPi * h * h * h);
+}
+
+/* Quintic spline shape and its q-derivatives, piecewise:
+ *   w(q) = (3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5   (q < 1)
+ *        = (3-q)^5 - 6 (2-q)^5                (1 <= q < 2)
+ *        = (3-q)^5                            (2 <= q < 3) */
+double quintic(double q, int deriv) {
+    double w = 0.0;
+    const double a[3] = {3.0, 2.0, 1.0}, c[3] = {1.0, -6.0, 15.0};
+    for (int k = 0; k < 3; ++k) {
+        const double t = a[k] - q;
+        if (t <= 0.0) continue;
+        const double t2 = t * t;
+        if (deriv == 0) w += c[k] * t2 * t2 * t;
+        if (deriv == 1) w += -5.0 * c[k] * t2 * t2;
+        if (deriv == 2) w += 20.0 * c[k] * t2 * t;
+    }
+    return w;
 }
 
 /* W(|r|, h) */
 double W(const OrcParams& P, double r) {
     const double q = r / P.h;
     const double s = sigma(P);
+    if (P.kernel == 2) return q >= 3.0 ? 0.0 : s * quintic(q, 0);
     if (q >= 2.0) return 0.0;
     if (P.kernel == 0) {
         if (q < 1.0) return s * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
@@ -83,6 +111,7 @@ double W(const OrcParams& P, double r) {
 double dWdr(const OrcParams& P, double r) {
     const double q = r / P.h;
     const double s = sigma(P);
+    if (P.kernel == 2) return q >= 3.0 ? 0.0 : s * quintic(q, 1) / P.h;
     if (q >= 2.0) return 0.0;
     if (P.kernel == 0) {
         if (q < 1.0) return s * (-3.0 * q + 2.25 * q * q) / P.h;
@@ -97,6 +126,7 @@ double dWdr(const OrcParams& P, double r) {
 double d2Wdr2(const OrcParams& P, double r) {
     const double q = r / P.h;
     const double s = sigma(P);
+    if (P.kernel == 2) return q >= 3.0 ? 0.0 : s * quintic(q, 2) / (P.h * P.h);
     if (q >= 2.0) return 0.0;
     if (P.kernel == 0) {
         if (q < 1.0) return s * (-3.0 + 4.5 * q) / (P.h * P.h);
@@ -139,7 +169,7 @@ struct Grid {
  * axis is too short for the stencil to visit each cell once, or if the grid
  * has more than 2^31 cells. */
 bool make_grid(const OrcParams& P, Grid& G) {
-    const double R = 2.0 * P.h;
+    const double R = support(P);
     G.stencil = P.cell_div;
     G.ncells = 1;
     for (int k = 0; k < 3; ++k) {
@@ -181,7 +211,7 @@ struct Nbrs {
 };
 
 bool in_support(const OrcParams& P, const double* d) {
-    const double R = 2.0 * P.h;
+    const double R = support(P);
     return dot(d, d, P.dim) < R * R;
 }
 

@@ -125,7 +125,8 @@ constexpr int kMaxNbrCap = 4096;
 int check_params(const sph_params* p, bool need_dt) {
     if (!p) return fail(SPH_EINVAL, "params is NULL");
     if (p->dim != 2 && p->dim != 3) return fail(SPH_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
-    if (p->kernel != SPH_CUBIC_SPLINE && p->kernel != SPH_WENDLAND_C2)
+    if (p->kernel != SPH_CUBIC_SPLINE && p->kernel != SPH_WENDLAND_C2 &&
+        p->kernel != SPH_QUINTIC_SPLINE)
         return fail(SPH_EINVAL, "unknown kernel %d", p->kernel);
     if (p->precision != SPH_FP64 && p->precision != SPH_FP32_MIXED)
         return fail(SPH_EINVAL, "unknown precision %d", p->precision);
@@ -149,8 +150,14 @@ int check_params(const sph_params* p, bool need_dt) {
     return SPH_OK;
 }
 
+// Support radius R = k h of the smoothing kernel: k = 3 for the quintic
+// spline, 2 otherwise.
+inline double support_radius(const sph_params* p) {
+    return (p->kernel == SPH_QUINTIC_SPLINE ? 3.0 : 2.0) * p->h;
+}
+
 int make_grid(const sph_params* p, sph::Grid* G, int64_t* ncells) {
-    const double R = 2.0 * p->h;
+    const double R = support_radius(p);
     *ncells = 1;
     std::memset(G, 0, sizeof *G);
     G->dim = p->dim;
@@ -375,19 +382,22 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
     double sigma;
     if (p->kernel == SPH_CUBIC_SPLINE)
         sigma = p->dim == 2 ? 10.0 / (7.0 * pi * h * h) : 1.0 / (pi * h * h * h);
+    else if (p->kernel == SPH_QUINTIC_SPLINE)
+        sigma = p->dim == 2 ? 7.0 / (478.0 * pi * h * h) : 1.0 / (120.0 * pi * h * h * h);
     else
         sigma = p->dim == 2 ? 7.0 / (4.0 * pi * h * h) : 21.0 / (16.0 * pi * h * h * h);
+    const double R = support_radius(p), R2 = R * R;
     sph::PairConst<T> C;
-    C.R2 = (T)(4.0 * h * h);
-    C.R2_d = 4.0 * h * h;
+    C.R2 = (T)R2;
+    C.R2_d = R2;
     C.inv_h_d = 1.0 / h;
     C.sigma_d = sigma;
     for (int k = 0; k < 3; ++k) {
         C.fix_scale[k] = G.cs[k] / (double)(1 << sph::kFixBits);
         C.fix_scale_f[k] = (float)C.fix_scale[k];
     }
-    C.R2_lo = (float)(4.0 * h * h * (1.0 - 1e-5));
-    C.R2_hi = (float)(4.0 * h * h * (1.0 + 1e-5));
+    C.R2_lo = (float)(R2 * (1.0 - 1e-5));
+    C.R2_hi = (float)(R2 * (1.0 + 1e-5));
     C.h = (T)h;
     C.inv_h = (T)(1.0 / h);
     C.sigma = (T)sigma;
@@ -773,10 +783,14 @@ int dispatch(const sph_params* p, Args&&... args) {
     if (p->dim == 2) {
         if (p->kernel == SPH_CUBIC_SPLINE)
             return f64 ? F<2, 0, double>::run(p, args...) : F<2, 0, float>::run(p, args...);
+        if (p->kernel == SPH_QUINTIC_SPLINE)
+            return f64 ? F<2, 2, double>::run(p, args...) : F<2, 2, float>::run(p, args...);
         return f64 ? F<2, 1, double>::run(p, args...) : F<2, 1, float>::run(p, args...);
     }
     if (p->kernel == SPH_CUBIC_SPLINE)
         return f64 ? F<3, 0, double>::run(p, args...) : F<3, 0, float>::run(p, args...);
+    if (p->kernel == SPH_QUINTIC_SPLINE)
+        return f64 ? F<3, 2, double>::run(p, args...) : F<3, 2, float>::run(p, args...);
     return f64 ? F<3, 1, double>::run(p, args...) : F<3, 1, float>::run(p, args...);
 }
 

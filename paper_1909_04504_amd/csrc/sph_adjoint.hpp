@@ -31,10 +31,24 @@ namespace sph {
 //   cubic, q < 1:  F = s2 (-3 + 2.25 q),          F1 = s4 2.25 / q
 //   cubic, q < 2:  F = -0.75 s2 (2-q)^2 / q,       F1 = s4 (1.5 (2-q) + 0.75 (2-q)^2/q) / q^2
 //   Wendland:      F = -5 s2 (1-q/2)^3,            F1 = 7.5 s4 (1-q/2)^2 / q
+//   quintic, q < 1: F = s2 (-120 + q^2 (120 - 50 q)), F1 = s4 (240 - 150 q)
+//   quintic, q < 3: F = s2 w'/q,                   F1 = s4 (w'' - w'/q) / q^2
+//     w' = -5 (3-q)^4 + 30 (2-q)_+^4,  w'' = 20 (3-q)^3 - 120 (2-q)_+^3
 // with s2 = sigma/h^2, s4 = sigma/h^4.
 template <int KERNEL, typename T>
 __device__ __forceinline__ void kernel_f_f1(T q, T inv_q, T s2, T s4, T* F, T* F1) {
-    if (KERNEL == 0) {
+    if (KERNEL == 2) {
+        if (q < T(1)) {
+            *F = s2 * (T(-120) + q * q * (T(120) - T(50) * q));
+            *F1 = s4 * (T(240) - T(150) * q);
+        } else {
+            const T t3 = T(3) - q, t2 = pos_part(T(2) - q);
+            const T dw = quintic_dw(q);
+            const T d2w = T(20) * t3 * t3 * t3 - T(120) * t2 * t2 * t2;
+            *F = s2 * dw * inv_q;
+            *F1 = s4 * (d2w - dw * inv_q) * inv_q * inv_q;
+        }
+    } else if (KERNEL == 0) {
         if (q < T(1)) {
             *F = s2 * (T(-3) + T(2.25) * q);
             *F1 = s4 * T(2.25) * inv_q;

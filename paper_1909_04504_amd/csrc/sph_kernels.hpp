@@ -7,20 +7,23 @@
 //
 // Design for CDNA4 (wave64, 256 CUs in 8 XCDs):
 //  * Particles are kept sorted by cell key, so the particles of a stencil row
-//    of cells are contiguous and every pair loop walks contiguous,
+//    of cells are contiguous and every cell walk reads contiguous,
 //    cache-resident slot ranges.  The sort is a counting sort on cell keys:
 //    integer atomics count particles per cell, a two-kernel scan turns counts
 //    into cell offsets, an atomic scatter groups particles by cell and a
 //    per-cell rank (number of smaller previous indices in the same cell)
 //    makes the result identical to a stable sort, hence deterministic.
-//  * Pair records are packed per sorted slot: (delta, m) and (v) as 4-vectors
-//    and (rho, P = p/rho^2) as a 2-vector, where delta is the position
-//    relative to the origin of the particle's own cell.  Separations are
-//    r_ij = (delta_i - delta_j) - o cs, o the stencil offset of j's cell, so
-//    swapping i and j negates every rounded operation: r_ji = -r_ij bitwise
-//    and the neighbour predicate is exactly symmetric.  In mixed precision
-//    delta is float: a cell-relative float keeps ~1e-9 absolute accuracy
-//    where an absolute float position would keep ~1e-7.
+//  * Pair records are packed per sorted slot: the position record, the
+//    velocity as a 4-vector and (rho, P = p/rho^2) as a 2-vector.  FP64
+//    records hold the absolute position; mixed-precision records hold
+//    fixed-point offsets from the centre of the particle's cell, so that a
+//    separation is an exact integer difference.  Either way swapping i and j
+//    negates the separation bitwise and the neighbour predicate (decided in
+//    FP64) is exactly symmetric.
+//  * Each step builds neighbour lists once (one cell walk, or one wave per
+//    cell in 2D) and the density and momentum passes read them densely, in
+//    the walk's order; a particle with more neighbours than the list
+//    capacity is walked instead, with bitwise the same result.
 //  * No floating-point atomics anywhere: every sum is formed by one thread in
 //    a fixed order, so results are bitwise reproducible run to run.
 //  * Integration (kick, drift, wrap) is FP64 with contraction disabled, so
@@ -168,11 +171,22 @@ __device__ __forceinline__ double sqrt_newton(double x) {
 __device__ __forceinline__ double density_sqrt(double x, float) { return sqrt_newton(x); }
 __device__ __forceinline__ double density_sqrt(double x, double) { return sqrt(x); }
 
-// Smoothing kernel W(q) = sigma w(q), q = r/h, support q < 2.
+// Smoothing kernel W(q) = sigma w(q), q = r/h, support q < 2 (q < 3 for
+// the quintic spline).
 //   cubic spline (M4):  1 - 1.5 q^2 + 0.75 q^3 (q < 1);  0.25 (2 - q)^3 (q < 2)
 //   Wendland C2:        (1 - q/2)^4 (2 q + 1)
+//   quintic spline:     (3-q)^5 - 6 (2-q)_+^5 + 15 (1-q)_+^5
 // The cubic spline is evaluated as 0.25 (2-q)^3 - (1-q)_+^3, the same
 // polynomial as 1 - 1.5 q^2 + 0.75 q^3 on q < 1 without a second branch.
+template <typename T>
+__device__ __forceinline__ T pow5(T t) {
+    const T t2 = t * t;
+    return t2 * t2 * t;
+}
+template <typename T>
+__device__ __forceinline__ T pos_part(T t) {
+    return t > T(0) ? t : T(0);
+}
 template <int KERNEL, typename T>
 __device__ __forceinline__ T kernel_w(T q, T sigma) {
     if (KERNEL == 0) {
@@ -180,6 +194,9 @@ __device__ __forceinline__ T kernel_w(T q, T sigma) {
         T t1 = T(1) - q;
         t1 = t1 > T(0) ? t1 : T(0);
         return sigma * (T(0.25) * t2 * t2 * t2 - t1 * t1 * t1);
+    } else if (KERNEL == 2) {
+        return sigma * (pow5(T(3) - q) - T(6) * pow5(pos_part(T(2) - q)) +
+                        T(15) * pow5(pos_part(T(1) - q)));
     } else {
         const T t = T(1) - T(0.5) * q;
         const T t2 = t * t;
@@ -190,12 +207,24 @@ __device__ __forceinline__ T kernel_w(T q, T sigma) {
 // F(q) = (dW/dr) / r, so that grad_i W_ij = F r_ij.
 //   cubic:    sigma/h^2 (-3 + 2.25 q)  (q < 1);  -0.75 sigma/h^2 (2-q)^2 / q  (q < 2)
 //   Wendland: -5 sigma/h^2 (1 - q/2)^3
+//   quintic:  sigma/h^2 (-120 + q^2 (120 - 50 q))  (q < 1);
+//             sigma/h^2 (-5 (3-q)^4 + 30 (2-q)_+^4) / q  (q < 3)
+// (the q < 1 form is w'(q)/q expanded, without the division at q -> 0).
+template <typename T>
+__device__ __forceinline__ T quintic_dw(T q) {  // w'(q) for q >= 1
+    const T t3 = T(3) - q, t2 = pos_part(T(2) - q);
+    const T a = t3 * t3, b = t2 * t2;
+    return T(-5) * a * a + T(30) * b * b;
+}
 template <int KERNEL, typename T>
 __device__ __forceinline__ T kernel_f(T q, T sigma_h2) {
     if (KERNEL == 0) {
         const T t = T(2) - q;
         if (q < T(1)) return sigma_h2 * (T(-3) + T(2.25) * q);
         return T(-0.75) * sigma_h2 * t * t * p_rcp(q);
+    } else if (KERNEL == 2) {
+        if (q < T(1)) return sigma_h2 * (T(-120) + q * q * (T(120) - T(50) * q));
+        return sigma_h2 * quintic_dw(q) * p_rcp(q);
     } else {
         const T t = T(1) - T(0.5) * q;
         return T(-5) * sigma_h2 * t * t * t;
@@ -212,6 +241,10 @@ __device__ __forceinline__ T kernel_f_r2(T r2, const PairConst<T>& C) {
         const T t = T(2) - q;
         const T inner = C.sigma_h2 * (T(-3) + T(2.25) * q);
         const T outer = T(-0.75) * C.sigma_h2 * t * t * (C.h * rinv);
+        return q < T(1) ? inner : outer;
+    } else if (KERNEL == 2) {
+        const T inner = C.sigma_h2 * (T(-120) + q * q * (T(120) - T(50) * q));
+        const T outer = C.sigma_h2 * quintic_dw(q) * (C.h * rinv);
         return q < T(1) ? inner : outer;
     } else {
         const T t = T(1) - T(0.5) * q;
@@ -886,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
 }
 
 // Pack pair records of an already sorted state (standalone evaluations):
-// key = cell of x, (delta, m), (u), and (rho, p/rho^2) if with_rp.
+// key = cell of x, the position record, (u), and (rho, p/rho^2) if with_rp.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
                                                  uint32_t* __restrict__ skey,

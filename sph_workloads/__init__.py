@@ -31,6 +31,7 @@ import numpy as np
 
 CUBIC = 0
 WENDLAND = 1
+QUINTIC = 2
 FLUID = 0
 WALL = 1
 
@@ -38,7 +39,7 @@ WALL = 1
 @dataclasses.dataclass
 class Params:
     dim: int
-    kernel: int            # CUBIC or WENDLAND
+    kernel: int            # CUBIC, WENDLAND (support 2h) or QUINTIC (support 3h)
     h: float               # smoothing length (support radius 2h)
     rho0: float
     c0: float

@@ -34,6 +34,21 @@ def test_rollout_gradient_fp64_matches_oracle(k, nbr_cap):
     assert gnu == pytest.approx(gnu_ref, rel=1e-10)
 
 
+def test_rollout_gradient_quintic_fp64_and_mixed():
+    """Quintic spline (support 3h): the FP64 rollout gradient against the
+    oracle adjoint, and the mixed-precision one at the mixed bar."""
+    p, s = W.taylor_green(16, jitter=0.25, seed=5, kernel=W.QUINTIC, hdx=1.0)
+    nsteps = 6
+    gu_ref, gnu_ref, ke_ref = oracle.adjoint_ke(p, s.x, s.u, s.m, s.ptype, nsteps)
+    ke, gu, gnu = _grads(p, s, nsteps, 3, sph.FP64)
+    assert ke == pytest.approx(ke_ref, rel=1e-12)
+    assert normwise(gu, gu_ref) < 1e-10
+    assert gnu == pytest.approx(gnu_ref, rel=1e-10)
+    ke, gu, gnu = _grads(p, s, nsteps, 3, sph.FP32_MIXED)
+    assert normwise(gu, gu_ref) < 1e-3
+    assert gnu == pytest.approx(gnu_ref, rel=1e-3)
+
+
 def test_rollout_gradient_3d_walls_fp64():
     p, s = W.dam_break_3d(dx=0.05)
     rng = np.random.default_rng(4)

@@ -36,6 +36,11 @@ def make_case(name):
         rng = np.random.default_rng(15)
         s.u[:, s.ptype == 0] = rng.normal(0, 0.3, size=(3, int((s.ptype == 0).sum())))
         return p, s
+    if name == "tg2d_quintic":
+        return W.taylor_green(50, jitter=0.3, seed=17, kernel=W.QUINTIC, hdx=1.0)
+    if name == "cube3d_quintic":
+        p, s = W.periodic_cube(n_side=16, jitter=0.3, sigma_u=0.1, seed=18, hdx=1.0)
+        return p.replace(kernel=W.QUINTIC), s
     if name == "box2d":
         # non-periodic 2D box with gravity, cubic spline
         p, s = W.taylor_green(40, jitter=0.3, seed=16)
@@ -47,7 +52,8 @@ def make_case(name):
     raise KeyError(name)
 
 
-CASES = ["tg2d", "tg2d_cd2", "cube3d", "cube3d_cd2", "dam3d", "box2d"]
+CASES = ["tg2d", "tg2d_cd2", "cube3d", "cube3d_cd2", "dam3d", "box2d", "tg2d_quintic",
+         "cube3d_quintic"]
 
 
 def gpu_sorted(p, s, prec):

@@ -29,6 +29,21 @@ def test_density_lattice_uniform_and_equals_lattice_sum():
     assert abs(rho[0] / p.rho0 - 1) < 1e-3
 
 
+def test_density_lattice_quintic_equals_lattice_sum():
+    """Quintic spline, support 3h with h = dx: the lattice sum over the 25
+    offsets with |r| < 3dx (a direct count; exact ties at 3dx excluded)."""
+    p, s = W.taylor_green(32, kernel=W.QUINTIC, hdx=1.0)
+    rho = oracle.density(p, s.x, s.m)
+    assert np.ptp(rho) < 1e-14 * rho.mean()
+    dx = 1.0 / 32
+    offs = [(i, j) for i in range(-3, 4) for j in range(-3, 4) if i * i + j * j < 9]
+    assert len(offs) == 25
+    r = np.array([np.hypot(i, j) * dx for i, j in offs])
+    expect = s.m[0] * oracle.kernel_w(p, r).sum()
+    assert abs(rho[0] - expect) < 1e-14
+    assert abs(rho[0] / p.rho0 - 1) < 1e-3
+
+
 def test_density_3d_lattice_wendland():
     p, s = W.periodic_cube(n_side=12, jitter=0.0, sigma_u=0.1)
     rho = oracle.density(p, s.x, s.m)
@@ -63,9 +78,10 @@ def _eval(p, s, v=None, pr=None):
     return rho, pr, oracle.momentum(p, s.x, s.u if v is None else v, s.m, s.ptype, rho, pr)
 
 
-def test_pairwise_antisymmetry_conserves_momentum():
+@pytest.mark.parametrize("kernel", [W.CUBIC, W.WENDLAND, W.QUINTIC])
+def test_pairwise_antisymmetry_conserves_momentum(kernel):
     """sum_i m_i (a_i - g) = 0 to roundoff: the pair terms are antisymmetric."""
-    p, s = W.taylor_green(24, jitter=0.3, seed=2)
+    p, s = W.taylor_green(24, jitter=0.3, seed=2, kernel=kernel)
     p = p.replace(g=(0.3, -1.0, 0.0))
     _, _, a = _eval(p, s)
     g = np.array(p.g[:2])[:, None]
@@ -136,6 +152,25 @@ def test_pressure_term_approximates_gradient(n_side, tol):
     a = oracle.momentum(p, s.x, np.zeros_like(s.u), s.m, s.ptype, rho, pr)
     exact = -2 * np.pi * P0 * np.cos(2 * np.pi * s.x[0]) / rho
     assert np.abs(a[0] - exact).max() < tol * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("n_side,tol_visc,tol_pres", [(32, 1.5e-2, 1.5e-2), (64, 1e-2, 3e-3)])
+def test_quintic_operators_approximate_derivatives(n_side, tol_visc, tol_pres):
+    """Quintic spline (support 3h, h = dx): the viscous term approximates
+    nu Laplacian(u) and the pressure term -grad(p)/rho on smooth fields, as
+    for the other kernels."""
+    p, s = W.taylor_green(n_side, kernel=W.QUINTIC, hdx=1.0)
+    rho = oracle.density(p, s.x, s.m)
+    u = np.zeros_like(s.x)
+    u[0] = np.sin(2 * np.pi * s.x[1])
+    a = oracle.momentum(p, s.x, u, s.m, s.ptype, rho, np.zeros(s.n))
+    exact = -p.nu * (2 * np.pi) ** 2 * u[0]
+    assert np.abs(a[0] - exact).max() < tol_visc * np.abs(exact).max()
+    P0 = 0.5
+    pr = P0 * np.sin(2 * np.pi * s.x[0])
+    a = oracle.momentum(p, s.x, np.zeros_like(s.u), s.m, s.ptype, rho, pr)
+    exact = -2 * np.pi * P0 * np.cos(2 * np.pi * s.x[0]) / rho
+    assert np.abs(a[0] - exact).max() < tol_pres * np.abs(exact).max()
 
 
 def test_walls_get_no_acceleration_but_act_as_sources():

@@ -55,6 +55,30 @@ def test_lattice_counts(dim, hdx, K):
     assert np.all(np.diff(off_b) == K)
 
 
+def _lattice_count(dim, R_over_dx):
+    """Points of the integer lattice with |n|^2 < (R/dx)^2, origin included:
+    a direct count, independent of any neighbour search."""
+    m = int(np.ceil(R_over_dx))
+    g = np.arange(-m, m + 1)
+    mesh = np.meshgrid(*([g] * dim), indexing="ij")
+    r2 = sum(c.astype(np.int64) ** 2 for c in mesh)
+    return int(np.count_nonzero(r2 < R_over_dx ** 2))
+
+
+@pytest.mark.parametrize("dim,hdx,cell_div", [(2, 1.0, 1), (2, 1.2, 2), (3, 1.0, 1), (3, 0.9, 2)])
+def test_lattice_counts_quintic_support(dim, hdx, cell_div):
+    """Quintic spline: support R = 3h.  On a perfect periodic lattice every
+    particle has the direct lattice count of points within 3h (R/dx = 3 in the
+    first 2D case: exact ties at distance 3dx excluded by the strict test)."""
+    n_side = 32 if dim == 2 else 16
+    p, x = _lattice_case(dim, n_side, hdx, kernel=W.QUINTIC, cell_div=cell_div)
+    K = _lattice_count(dim, 3.0 * hdx)
+    off, _ = oracle.neighbors(p, x)
+    assert np.all(np.diff(off) == K)
+    off_b, _ = oracle.neighbors(p, x, brute=True)
+    assert np.all(np.diff(off_b) == K)
+
+
 def _jittered(dim, n_side, jitter, seed, periodic=True, hdx=1.3, cell_div=1):
     rng = np.random.default_rng(seed)
     dx = 1.0 / n_side
