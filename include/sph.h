@@ -20,7 +20,8 @@
  *     SPH_FP32_MIXED evaluates the pair terms and the per-particle sums in
  *     single precision on cell-relative position offsets, and integrates
  *     positions and velocities in double precision; in that mode the arrays
- *     a, rho and p are float, otherwise double.  x, u and m are always double.
+ *     a, rho and p are float, otherwise double.  x, u and m are always double,
+ *     and so is rho under the continuity scheme (where it is integrated).
  *   - Streams: `stream` is a hipStream_t passed as void*; all work is enqueued
  *     on it in order.  Calls do not synchronise unless documented.
  *   - Errors: a negative sph_status; sph_last_error() gives a message (per
@@ -68,6 +69,13 @@ typedef enum {
 
 typedef enum { SPH_FLUID = 0, SPH_WALL = 1 } sph_particle_type;
 
+/* How sph_step obtains the density (Section 2).  Summation: rho is evaluated
+ * from the positions (eq. 2) and stepped with the predictor-corrector scheme.
+ * Continuity: rho is a state advanced by the continuity equation
+ * (eqn continuity:sph), drho_i/dt = sum_j m_j (u_i - u_j) . gradW_ij, with the
+ * Euler stage of the paper's dam-break example (Section 3). */
+typedef enum { SPH_SCHEME_SUMMATION = 0, SPH_SCHEME_CONTINUITY = 1 } sph_scheme;
+
 /* Run parameters.  gamma of the Tait equation is 7 (Section 2, eq. eos). */
 typedef struct {
     int32_t dim;          /* 2 or 3 */
@@ -90,6 +98,8 @@ typedef struct {
     double dt;            /* time step, > 0 (sph_step only) */
     double g[3];          /* body acceleration (eq. mom:sph, a_body) */
     double lo[3], hi[3];  /* domain box; the cell grid covers [lo, hi) */
+    int32_t scheme;       /* sph_scheme (sph_step only) */
+    int32_t reserved;     /* must be 0 */
 } sph_params;
 
 /* Particle arrays (device pointers, caller-owned). */
@@ -98,7 +108,8 @@ typedef struct {
     double* x[3];    /* positions */
     double* u[3];    /* velocities */
     void* a[3];      /* accelerations: double (SPH_FP64) or float (SPH_FP32_MIXED) */
-    void* rho;       /* density: double or float as a */
+    void* rho;       /* density: double or float as a; double under the
+                      * continuity scheme */
     void* p;         /* pressure: double or float as a */
     double* m;       /* masses */
     uint8_t* type;   /* sph_particle_type */
@@ -162,7 +173,18 @@ int sph_momentum(const sph_params* prm, sph_particles* pa, const uint32_t* cell_
  * prime_accel = 1 first evaluates rho, p, a at the input (x, u) (needed when
  * a is not yet known); 0 takes pa->a as given.  Particles end sorted by cell.
  * diag: NULL, or a device array of nsteps * (1 + dim) doubles receiving after
- * each step the kinetic energy sum m|u|^2/2 and the momentum sum m u. */
+ * each step the kinetic energy sum m|u|^2/2 and the momentum sum m u.
+ *
+ * With prm->scheme = SPH_SCHEME_CONTINUITY, pa->rho is an input state (the
+ * density of every particle, walls included) and each step is instead:
+ * neighbour rebuild at x;  p = EOS(rho) for all particles;
+ *   arho_i = sum_{j in N(i)} m_j (u_i - u_j) . gradW_ij  over all j for a
+ *   fluid particle and over fluid j for a wall particle;
+ *   a_i from the momentum equation for fluid particles (walls: 0);
+ * then for fluid particles u <- u + dt a, x <- wrap(x + dt u) (the new u);
+ * for every particle rho <- rho + dt arho.  Walls keep x and u = 0.  pa->p
+ * and pa->a hold the values of the last step's start; prime_accel is
+ * ignored. */
 int sph_step(const sph_params* prm, sph_particles* pa, int64_t nsteps, int prime_accel,
              void* ws, size_t ws_bytes, double* diag, void* stream);
 
@@ -175,7 +197,8 @@ int sph_step(const sph_params* prm, sph_particles* pa, int64_t nsteps, int prime
  * [lam_x (dim arrays of n)][lam_u (dim arrays)][lam_a (dim arrays)].
  * lam_out: the adjoint at the start of the segment, same layout, in the order
  * of ckpt.  *dJ_dnu (device double) is incremented by the viscosity
- * gradient of the segment.  lam_in and lam_out may not alias.
+ * gradient of the segment.  lam_in and lam_out may not alias.  Summation
+ * scheme only (SPH_EINVAL otherwise).
  * The first-step acceleration a^0 of a rollout is evaluated by
  * sph_accel_backward. */
 int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t k,
@@ -186,13 +209,14 @@ int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t 
  * (sorted or not): given lam_a (dim arrays of n doubles), ADDS (dA/dx)^T lam_a
  * to lam_x, (dA/du)^T lam_a to lam_u and (dA/dnu)^T lam_a to *dJ_dnu.
  * Arrays in the order of st.  st is not modified.  The workspace must be
- * sized with adjoint_k >= 1. */
+ * sized with adjoint_k >= 1.  Summation scheme only (SPH_EINVAL otherwise). */
 int sph_accel_backward(const sph_params* prm, const sph_particles* st, const double* lam_a,
                        double* lam_x, double* lam_u, double* dJ_dnu, void* ws, size_t ws_bytes,
                        void* stream);
 
 /* Interaction count (the throughput metric's unit): every density evaluation
- * (sph_density and each evaluation inside sph_step) adds sum_i |N(i)| (ordered
+ * (sph_density and each evaluation inside sph_step; with the continuity
+ * scheme, each step's pair pass) adds sum_i |N(i)| (ordered
  * pairs, each particle counted as its own neighbour) to a 64-bit counter in
  * the workspace.  Synchronises the stream, stores the counter in *total
  * (host), and zeroes it if reset = 1. */

@@ -74,6 +74,8 @@ def lib():
         L.orc_rhs_adjoint.argtypes = [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P]
         L.orc_adjoint_ke.argtypes = [_P, _i64, _P, _P, _P, _P, _i64, _P, _P, _P]
         L.orc_rollout_ke.argtypes = [_P, _i64, _P, _P, _P, _P, _i64, _P]
+        L.orc_step_continuity.argtypes = [_P, _i64, _P, _P, _P, _P, _P, _i64, _P, _P, _P]
+        L.orc_continuity.argtypes = [_P, _i64, _P, _P, _P, _P, _P]
         _lib = L
     return _lib
 
@@ -227,6 +229,30 @@ def step(p, x, u, m, ptype, nsteps, a=None, prime=True, want_diag=False, brute=F
     if want_diag:
         out["diag"] = dg[:nsteps]
     return out
+
+
+def step_continuity(p, x, u, rho, m, ptype, nsteps):
+    """nsteps of the paper's worked example (continuity density, EOS, momentum,
+    Euler stage).  Returns dict of x, u, rho after the steps and p, a, arho of
+    the last step's evaluation.  Inputs are not modified."""
+    x, u, rho = (_c(t, np.float64).copy() for t in (x, u, rho))
+    m, ptype = _c(m, np.float64), _c(ptype, np.uint8)
+    n = x.shape[1]
+    pr, a, arho = np.zeros(n), np.zeros_like(x), np.zeros(n)
+    _check(lib().orc_step_continuity(ctypes.byref(params(p)), n, _ptr(x), _ptr(u), _ptr(rho),
+                                     _ptr(m), _ptr(ptype), nsteps, _ptr(pr), _ptr(a),
+                                     _ptr(arho)))
+    return dict(x=x, u=u, rho=rho, p=pr, a=a, arho=arho)
+
+
+def continuity(p, x, v, m, ptype):
+    """d rho/dt of the continuity equation at (x, v)."""
+    x, v, m = _c(x, np.float64), _c(v, np.float64), _c(m, np.float64)
+    ptype = _c(ptype, np.uint8)
+    arho = np.zeros(x.shape[1])
+    _check(lib().orc_continuity(ctypes.byref(params(p)), x.shape[1], _ptr(x), _ptr(v), _ptr(m),
+                                _ptr(ptype), _ptr(arho)))
+    return arho
 
 
 def eval_subset(p, x, v, m, ptype, sub):

@@ -32,7 +32,7 @@ extern "C" {
 /* Parameters of one run.  Mirrored by a ctypes Structure in oracle/__init__.py */
 struct OrcParams {
     int32_t dim;         /* 2 or 3 */
-    int32_t kernel;      /* 0 = cubic spline (M4), 1 = Wendland C2 */
+    int32_t kernel;      /* 0 = cubic spline (M4), 1 = Wendland C2, 2 = quintic spline */
     int32_t cell_div;    /* cells per support radius along an axis (>= 1) */
     int32_t brute;       /* 1: brute-force neighbour sets; 0: cell list */
     int32_t periodic[3];
@@ -377,6 +377,33 @@ bool evaluate(const OrcParams& P, int64_t n, const double* x, const double* v, c
     return true;
 }
 
+/* ---- Continuity density: the paper's worked example (its equation
+ * listing and Euler stepper) ----
+ * d rho_i / dt = sum_j m_j (v_i - v_j) . gradW_ij (eqn continuity:sph), over
+ * every neighbour for fluid destinations and over fluid neighbours only for
+ * solid (wall) destinations, as the example's equation groups state. */
+void continuity(const OrcParams& P, int64_t n, const double* x, const double* v, const double* m,
+                const uint8_t* type, const Nbrs& N, double* arho) {
+    const int dim = P.dim;
+    double d[3];
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t b = N.off[i]; b < N.off[i + 1]; ++b) {
+            const int64_t j = N.idx[b];
+            if (j == i) continue; /* v_ii = 0 */
+            if (type[i] != 0 && type[j] != 0) continue;
+            separation(P, n, x, i, j, d);
+            const double r = std::sqrt(dot(d, d, dim));
+            if (r == 0.0) continue; /* gradW(0) = 0 */
+            const double f = dWdr(P, r) / r;
+            double vg = 0.0;
+            for (int k = 0; k < dim; ++k) vg += (v[k * n + i] - v[k * n + j]) * f * d[k];
+            s += m[j] * vg;
+        }
+        arho[i] = s;
+    }
+}
+
 /* Periodic wrap into [lo, hi) (A14) */
 double wrap(const OrcParams& P, double x, int k) {
     if (!P.periodic[k]) return x;
@@ -621,6 +648,54 @@ int orc_step(const OrcParams* P, int64_t n, double* x, double* u, double* a, con
                 u[k * n + i] = type[i] != 0 ? 0.0 : u[k * n + i] + 0.5 * dt * a[k * n + i];
         if (diag) diagnostics(*P, n, u, m, diag + s * (1 + dim));
     }
+    return 0;
+}
+
+/* Steps of the paper's worked example: accelerations at the start of the
+ * step from (x, u, rho) -- p = EOS(rho) on every particle, d rho/dt by the
+ * continuity equation, a by the momentum equation (fluid; walls a = 0) --
+ * then the Euler stage u += dt a; x += dt u (with the new u, then the
+ * periodic wrap); rho += dt d rho/dt.  Walls keep u = 0 and their position.
+ * p, a and arho (if not NULL) receive the values of the last step's
+ * evaluation. */
+int orc_step_continuity(const OrcParams* P, int64_t n, double* x, double* u, double* rho,
+                        const double* m, const uint8_t* type, int64_t nsteps, double* p_out,
+                        double* a_out, double* arho_out) {
+    const int dim = P->dim;
+    const double dt = P->dt;
+    std::vector<double> p(n), a((size_t)dim * n), arho(n);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        Nbrs N;
+        if (!neighbours(*P, n, x, N)) return -1;
+        for (int64_t i = 0; i < n; ++i) p[i] = eos(*P, rho[i]);
+        continuity(*P, n, x, u, m, type, N, arho.data());
+        momentum(*P, n, x, u, m, type, rho, p.data(), N, a.data());
+        for (int64_t i = 0; i < n; ++i) {
+            for (int k = 0; k < dim; ++k) {
+                if (type[i] != 0) {
+                    u[k * n + i] = 0.0;
+                    continue;
+                }
+                u[k * n + i] = u[k * n + i] + dt * a[k * n + i];
+                x[k * n + i] = wrap(*P, x[k * n + i] + dt * u[k * n + i], k);
+            }
+            rho[i] = rho[i] + dt * arho[i];
+        }
+    }
+    if (nsteps > 0) {
+        if (p_out) std::copy(p.begin(), p.end(), p_out);
+        if (a_out) std::copy(a.begin(), a.end(), a_out);
+        if (arho_out) std::copy(arho.begin(), arho.end(), arho_out);
+    }
+    return 0;
+}
+
+/* d rho/dt alone at (x, v) (pins and parity tests). */
+int orc_continuity(const OrcParams* P, int64_t n, const double* x, const double* v,
+                   const double* m, const uint8_t* type, double* arho) {
+    Nbrs N;
+    if (!neighbours(*P, n, x, N)) return -1;
+    continuity(*P, n, x, v, m, type, N, arho);
     return 0;
 }
 

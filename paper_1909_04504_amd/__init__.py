@@ -21,6 +21,7 @@ from . import build as _build
 SPH_OK, SPH_EINVAL, SPH_EWORKSPACE, SPH_ECAPACITY = 0, -1, -2, -3
 SPH_EDOMAIN, SPH_ENONFINITE, SPH_EDEVICE = -4, -5, -6
 FP64, FP32_MIXED = 0, 1
+SUMMATION, CONTINUITY = 0, 1  # sph_params.scheme
 
 _d = ctypes.c_double
 _i32 = ctypes.c_int32
@@ -38,7 +39,8 @@ class Params(ctypes.Structure):
     _fields_ = [("dim", _i32), ("kernel", _i32), ("precision", _i32), ("cell_div", _i32),
                 ("periodic", _i32 * 3), ("nbr_cap", _i32),
                 ("h", _d), ("rho0", _d), ("c0", _d), ("nu", _d), ("eta", _d), ("dt", _d),
-                ("g", _d * 3), ("lo", _d * 3), ("hi", _d * 3)]
+                ("g", _d * 3), ("lo", _d * 3), ("hi", _d * 3),
+                ("scheme", _i32), ("reserved", _i32)]
 
 
 class Particles(ctypes.Structure):
@@ -96,6 +98,8 @@ def make_params(p, precision: int = FP64, nbr_cap: int = 0) -> Params:
         c.periodic[k] = int(p.periodic[k])
         c.g[k], c.lo[k], c.hi[k] = float(p.g[k]), float(p.lo[k]), float(p.hi[k])
     c.nbr_cap = int(nbr_cap)
+    c.scheme = int(getattr(p, "scheme", 0))
+    c.reserved = 0
     c.h, c.rho0, c.c0, c.nu, c.eta, c.dt = p.h, p.rho0, p.c0, p.nu, p.eta, p.dt
     return c
 
@@ -114,25 +118,44 @@ def _dev(v, dtype, device) -> torch.Tensor:
 class DeviceParticles:
     """Device arrays of one particle set (SoA; vectors as (dim, n) tensors)."""
 
-    def __init__(self, x, u, m, ptype, pid, precision: int = FP64, a=None, device="cuda"):
+    def __init__(self, x, u, m, ptype, pid, precision: int = FP64, a=None, device="cuda",
+                 rho=None, scheme: int = SUMMATION):
         T = pair_dtype(precision)
+        # rho is FP64 under the continuity scheme (an integrated state)
+        TR = torch.float64 if scheme == CONTINUITY else T
         self.precision = precision
         self.x = _dev(x, torch.float64, device)
         self.u = _dev(u, torch.float64, device)
         self.dim, self.n = self.x.shape
         self.a = (torch.zeros((self.dim, self.n), dtype=T, device=device) if a is None else
                   _dev(a, T, device))
-        self.rho = torch.zeros(self.n, dtype=T, device=device)
+        # rho is an output of the summation scheme and a state (input) of the
+        # continuity scheme
+        self.rho = (torch.zeros(self.n, dtype=TR, device=device) if rho is None else
+                    _dev(rho, TR, device))
         self.p = torch.zeros(self.n, dtype=T, device=device)
         self.m = _dev(m, torch.float64, device)
         self.type = _dev(ptype, torch.uint8, device)
         self.id = _dev(pid, torch.int32, device)
 
     @classmethod
-    def from_state(cls, s, precision: int = FP64, device="cuda"):
-        return cls(s.x, s.u, s.m, s.ptype, s.pid, precision, device=device)
+    def from_state(cls, s, precision: int = FP64, device="cuda", scheme: int = SUMMATION):
+        return cls(s.x, s.u, s.m, s.ptype, s.pid, precision, device=device,
+                   rho=getattr(s, "rho", None), scheme=scheme)
 
-    def struct(self) -> Particles:
+    def struct(self, prm: Optional[Params] = None) -> Particles:
+        """The C view of these arrays; with prm, first checks that their
+        element types are the ones prm implies (a mismatch would make the
+        library read past the ends of the arrays)."""
+        if prm is not None:
+            T = pair_dtype(prm.precision)
+            TR = torch.float64 if prm.scheme == CONTINUITY else T
+            if (prm.dim != self.dim or self.a.dtype != T or self.p.dtype != T
+                    or self.rho.dtype != TR):
+                raise ValueError(
+                    f"particle arrays (dim {self.dim}, a {self.a.dtype}, rho "
+                    f"{self.rho.dtype}) do not match the parameters (dim {prm.dim}, "
+                    f"precision {prm.precision}, scheme {prm.scheme})")
         c = Particles()
         c.n = self.n
         for k in range(self.dim):
@@ -187,7 +210,7 @@ def cell_arrays(prm: Params, device="cuda"):
 
 def bin_sort(prm: Params, dp: DeviceParticles, ws: torch.Tensor, cell_start, cell_end,
              stream=None):
-    s = dp.struct()
+    s = dp.struct(prm)
     _rc(lib().sph_bin_sort(ctypes.byref(prm), ctypes.byref(s), ws.data_ptr(), ws.numel(),
                            cell_start.data_ptr(), cell_end.data_ptr(), _stream(stream)))
 
@@ -196,7 +219,7 @@ def neighbors(prm: Params, dp: DeviceParticles, cell_start, cell_end, capacity: 
               nbr: Optional[torch.Tensor], ws: torch.Tensor, stream=None) -> int:
     """Fills offsets (int64, n+1) and nbr (int32, capacity); returns the total.
     Raises SphError(SPH_ECAPACITY) with .total set if capacity is too small."""
-    s = dp.struct()
+    s = dp.struct(prm)
     total = ctypes.c_int64()
     rc = lib().sph_neighbors(ctypes.byref(prm), ctypes.byref(s), cell_start.data_ptr(),
                              cell_end.data_ptr(), capacity, offsets.data_ptr(),
@@ -211,39 +234,39 @@ def neighbors(prm: Params, dp: DeviceParticles, cell_start, cell_end, capacity: 
 
 
 def density(prm, dp, cell_start, cell_end, ws, stream=None):
-    s = dp.struct()
+    s = dp.struct(prm)
     _rc(lib().sph_density(ctypes.byref(prm), ctypes.byref(s), cell_start.data_ptr(),
                           cell_end.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
 
 
 def eos(prm, dp, stream=None):
-    s = dp.struct()
+    s = dp.struct(prm)
     _rc(lib().sph_eos(ctypes.byref(prm), ctypes.byref(s), _stream(stream)))
 
 
 def momentum(prm, dp, cell_start, cell_end, ws, stream=None):
-    s = dp.struct()
+    s = dp.struct(prm)
     _rc(lib().sph_momentum(ctypes.byref(prm), ctypes.byref(s), cell_start.data_ptr(),
                            cell_end.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
 
 
 def step(prm, dp, nsteps: int, ws, prime: bool = True, diag: Optional[torch.Tensor] = None,
          stream=None):
-    s = dp.struct()
+    s = dp.struct(prm)
     _rc(lib().sph_step(ctypes.byref(prm), ctypes.byref(s), nsteps, 1 if prime else 0,
                        ws.data_ptr(), ws.numel(), diag.data_ptr() if diag is not None else None,
                        _stream(stream)))
 
 
 def step_backward(prm, ckpt: DeviceParticles, k: int, lam_in, lam_out, dJ_dnu, ws, stream=None):
-    s = ckpt.struct()
+    s = ckpt.struct(prm)
     _rc(lib().sph_step_backward(ctypes.byref(prm), ctypes.byref(s), k, lam_in.data_ptr(),
                                 lam_out.data_ptr(), dJ_dnu.data_ptr(), ws.data_ptr(), ws.numel(),
                                 _stream(stream)))
 
 
 def accel_backward(prm, st: DeviceParticles, lam_a, lam_x, lam_u, dJ_dnu, ws, stream=None):
-    s = st.struct()
+    s = st.struct(prm)
     _rc(lib().sph_accel_backward(ctypes.byref(prm), ctypes.byref(s), lam_a.data_ptr(),
                                  lam_x.data_ptr(), lam_u.data_ptr(), dJ_dnu.data_ptr(),
                                  ws.data_ptr(), ws.numel(), _stream(stream)))

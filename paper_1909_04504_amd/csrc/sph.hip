@@ -56,12 +56,12 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + sph::kBlock - 1) 
 enum KernelId {
     K_FILL, K_HASH, K_CHUNK_SUM, K_CHUNK_SCAN, K_SCATTER, K_RANK_GATHER, K_PACK, K_DENSITY,
     K_MOMENTUM, K_EOS, K_NBR_COUNT, K_NBR_FILL, K_CELL_RANGES, K_COPY, K_DIAG, K_ADJ_SEED,
-    K_ADJ_PAIR1, K_ADJ_PAIR2, K_ADJ_REDUCE, K_ADJ_KICK, K_NLIST, K_COUNT
+    K_ADJ_PAIR1, K_ADJ_PAIR2, K_ADJ_REDUCE, K_ADJ_KICK, K_NLIST, K_CONT, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "fill", "drift_hash", "chunk_sum", "chunk_scan", "scatter", "rank_gather", "pack",
     "density", "momentum", "eos", "nbr_count", "nbr_fill", "cell_ranges", "copy_state", "diag",
-    "adj_seed", "adj_pair1", "adj_pair2", "adj_reduce", "adj_kick", "nlist"};
+    "adj_seed", "adj_pair1", "adj_pair2", "adj_reduce", "adj_kick", "nlist", "cont_momentum"};
 
 struct Timer {
     bool on = false;
@@ -131,6 +131,9 @@ int check_params(const sph_params* p, bool need_dt) {
     if (p->precision != SPH_FP64 && p->precision != SPH_FP32_MIXED)
         return fail(SPH_EINVAL, "unknown precision %d", p->precision);
     if (p->cell_div != 1 && p->cell_div != 2) return fail(SPH_EINVAL, "cell_div must be 1 or 2");
+    if (p->scheme != SPH_SCHEME_SUMMATION && p->scheme != SPH_SCHEME_CONTINUITY)
+        return fail(SPH_EINVAL, "unknown scheme %d", p->scheme);
+    if (p->reserved != 0) return fail(SPH_EINVAL, "reserved must be 0");
     if (p->nbr_cap > kMaxNbrCap)
         return fail(SPH_EINVAL, "nbr_cap must be at most %d (got %d)", kMaxNbrCap, p->nbr_cap);
     if (!(p->h > 0) || !std::isfinite(p->h)) return fail(SPH_EINVAL, "h must be > 0");
@@ -283,7 +286,7 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
         so.m = take(8 * N);
         so.type = take(N);
         so.id = take(4 * N);
-        so.rho = take(T * N);
+        so.rho = take(8 * N);
         so.p = take(T * N);
         return so;
     };
@@ -343,7 +346,11 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
     return L;
 }
 
-sph::State user_state(const sph_particles* pa) {
+// rho is FP64 under the continuity scheme (an integrated state), else of the
+// pair type.
+inline int rho_is_f64(const sph_params* p) { return p->scheme == SPH_SCHEME_CONTINUITY; }
+
+sph::State user_state(const sph_particles* pa, const sph_params* p) {
     sph::State s;
     for (int k = 0; k < 3; ++k) {
         s.x[k] = pa->x[k];
@@ -355,6 +362,7 @@ sph::State user_state(const sph_particles* pa) {
     s.m = pa->m;
     s.type = pa->type;
     s.id = pa->id;
+    s.rho64 = rho_is_f64(p);
     return s;
 }
 
@@ -372,6 +380,7 @@ sph::State ws_state(char* ws, const StateOff& L, const sph_params* p, int64_t n)
     s.m = (double*)(ws + L.m);
     s.type = (uint8_t*)(ws + L.type);
     s.id = (int32_t*)(ws + L.id);
+    s.rho64 = rho_is_f64(p);
     return s;
 }
 
@@ -512,8 +521,10 @@ struct Engine {
     // gather of src into dst in sorted order with pair records packed.
     // hashed: src already holds the drifted positions with keys and counts
     // (from the epilogue of the previous momentum launch).
+    // eos: gather rho, and form p and the (rho, p/rho^2) records from it
+    // (continuity scheme).
     int sort_into(const sph::State& src, const sph::State& dst, bool drift, bool copy_derived,
-                  bool hashed = false) {
+                  bool hashed = false, bool eos = false) {
         const unsigned nb = blocks_for(n);
         using TA = T;
         if (!hashed) {
@@ -528,7 +539,8 @@ struct Engine {
         }
         launch(K_RANK_GATHER, sph::k_rank_gather<DIM, T>, nb, st, n, tmp(), key(), start(), src, dst, G,
                                                              perm(), skey(), pos(), vel(),
-                                                             copy_derived ? 1 : 0, typetape);
+                                                             copy_derived ? 1 : 0, typetape, C,
+                                                             rp(), eos ? 1 : 0);
         return launch_check("k_rank_gather");
     }
 
@@ -564,7 +576,7 @@ struct Engine {
         if (L.cap) SPH_TRY(nlist(cs, ce, true));
         with_reach([&](auto R) {
             launch(K_DENSITY, sph::k_density<DIM, decltype(R)::value, KERNEL, T>, blocks_for(n), st,
-                n, G, C, skey(), pos(), cs, ce, list_or_null(), lcnt(), L.cap, (T*)s.rho,
+                n, G, C, skey(), pos(), cs, ce, list_or_null(), lcnt(), L.cap, s.rho, s.rho64,
                 (T*)s.p, rp(), with_eos ? 1 : 0, L.cap ? 0 : 1, pairs());
         });
         return launch_check("k_density");
@@ -604,7 +616,7 @@ struct Engine {
     // --- entry points ---------------------------------------------------
 
     int bin_sort(sph_particles* pa, uint32_t* cs_out, uint32_t* ce_out) {
-        const sph::State user = user_state(pa);
+        const sph::State user = user_state(pa, prm);
         const sph::State tmp_state = ws_state(ws, L.s1, prm, n);
         SPH_TRY(zero_counts());
         SPH_TRY(sort_into(user, tmp_state, false, true));
@@ -614,26 +626,27 @@ struct Engine {
     }
 
     int density_only(sph_particles* pa, const uint32_t* cs, const uint32_t* ce) {
-        const sph::State user = user_state(pa);
+        const sph::State user = user_state(pa, prm);
         SPH_TRY(pack(user, false));
         return density(user, cs, ce, false);
     }
 
     int momentum_only(sph_particles* pa, const uint32_t* cs, const uint32_t* ce) {
-        const sph::State user = user_state(pa);
+        const sph::State user = user_state(pa, prm);
         SPH_TRY(pack(user, true));
         if (L.cap) SPH_TRY(nlist(cs, ce, false));
         return momentum(user, cs, ce, false);
     }
 
     int eos_only(sph_particles* pa) {
-        launch(K_EOS, sph::k_eos<T>, blocks_for(n), st, n, C, (const T*)pa->rho, (T*)pa->p);
+        launch(K_EOS, sph::k_eos<T>, blocks_for(n), st, n, C, (const void*)pa->rho,
+               rho_is_f64(prm), (T*)pa->p);
         return launch_check("k_eos");
     }
 
     int neighbors(const sph_particles* pa, const uint32_t* cs, const uint32_t* ce, int64_t capacity,
                   int64_t* offsets, int32_t* nbr, int64_t* total) {
-        const sph::State user = user_state(pa);
+        const sph::State user = user_state(pa, prm);
         SPH_TRY(pack(user, false));
         {
         with_reach([&](auto R) {
@@ -659,7 +672,7 @@ struct Engine {
     }
 
     int step(sph_particles* pa, int64_t nsteps, int prime, double* diag_out) {
-        const sph::State user = user_state(pa);
+        const sph::State user = user_state(pa, prm);
         const sph::State wst = ws_state(ws, L.s1, prm, n);
         sph::State cur = user, nxt = wst;
         const uint32_t* cs = start();
@@ -680,6 +693,40 @@ struct Engine {
             SPH_TRY(momentum(nxt, cs, ce, true, !last, diag_out ? diag_out + s * (1 + DIM) : nullptr));
             std::swap(cur, nxt);
             hashed = !last;
+        }
+        if (cur.m != user.m) SPH_TRY(copy(cur, user));
+        return SPH_OK;
+    }
+
+    // Continuity scheme (the paper's dam-break example): per step, sort
+    // with rho gathered and p = EOS(rho), lists, then one pass for drho/dt and
+    // a with the Euler stage and the next step's hash in its epilogue.
+    int step_continuity(sph_particles* pa, int64_t nsteps, double* diag_out) {
+        const sph::State user = user_state(pa, prm);
+        const sph::State wst = ws_state(ws, L.s1, prm, n);
+        sph::State cur = user, nxt = wst;
+        const uint32_t* cs = start();
+        const uint32_t* ce = start() + 1;
+        const unsigned nb = blocks_for(n);
+        double* part = (double*)(ws + L.diag);
+        SPH_TRY(zero_counts());
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const bool last = s == nsteps - 1;
+            double* dg = diag_out ? diag_out + s * (1 + DIM) : nullptr;
+            SPH_TRY(sort_into(cur, nxt, false, false, s > 0, true));
+            if (L.cap) SPH_TRY(nlist(cs, ce, true));
+            with_reach([&](auto R) {
+                launch(K_CONT, sph::k_cont_momentum<DIM, decltype(R)::value, KERNEL, T>, nb, st, n,
+                       G, C, skey(), pos(), vel(), rp(), (const uint8_t*)nxt.type, cs, ce,
+                       list_or_null(), lcnt(), L.cap, nxt, 1, last ? 0 : 1, prm->dt, key(),
+                       counts(), flags(), dg ? part : nullptr, L.cap ? 0 : 1, pairs());
+            });
+            SPH_TRY(launch_check("k_cont_momentum"));
+            if (dg) {
+                launch(K_DIAG, sph::k_diag_final<DIM>, 1, st, (int)nb, part, dg);
+                SPH_TRY(launch_check("k_diag_final"));
+            }
+            std::swap(cur, nxt);
         }
         if (cur.m != user.m) SPH_TRY(copy(cur, user));
         return SPH_OK;
@@ -728,7 +775,7 @@ struct Engine {
     // k recomputed steps from the checkpoint, then their reverse.
     int step_backward(const sph_particles* ck, int64_t k, const double* lam_in, double* lam_out,
                       double* dJ) {
-        const sph::State user = user_state(ck);
+        const sph::State user = user_state(ck, prm);
         const sph::State s1 = ws_state(ws, L.s1, prm, n);
         const sph::State s2 = ws_state(ws, L.s2, prm, n);
         SPH_TRY(copy(user, s2));
@@ -763,7 +810,7 @@ struct Engine {
     // Adjoint of one acceleration evaluation at the (unsorted) state st.
     int accel_backward(const sph_particles* stp, const double* lam_a, double* lam_x,
                        double* lam_u, double* dJ) {
-        const sph::State user = user_state(stp);
+        const sph::State user = user_state(stp, prm);
         const sph::State s1 = ws_state(ws, L.s1, prm, n);
         default_records();
         SPH_TRY(zero_counts());
@@ -876,6 +923,7 @@ struct RunStep {
                    size_t wb, double* diag, void* st) {
         Engine<DIM, KERNEL, T> E;
         SPH_TRY(make_engine(p, pa, ws, wb, st, &E));
+        if (p->scheme == SPH_SCHEME_CONTINUITY) return E.step_continuity(pa, nsteps, diag);
         return E.step(pa, nsteps, prime, diag);
     }
 };
@@ -1003,6 +1051,8 @@ int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t 
     if (k < 1) return fail(SPH_EINVAL, "k must be >= 1");
     if (!lam_in || !lam_out || !dJ_dnu) return fail(SPH_EINVAL, "lam_in, lam_out or dJ_dnu is NULL");
     if (lam_in == lam_out) return fail(SPH_EINVAL, "lam_in and lam_out may not alias");
+    if (prm->scheme != SPH_SCHEME_SUMMATION)
+        return fail(SPH_EINVAL, "the adjoint covers the summation scheme only");
     return dispatch<RunStepBackward>(prm, ckpt, k, lam_in, lam_out, dJ_dnu, ws, ws_bytes, stream);
 }
 
@@ -1014,6 +1064,8 @@ int sph_accel_backward(const sph_params* prm, const sph_particles* st, const dou
     SPH_TRY(check_particles(prm, st));
     if (!lam_a || !lam_x || !lam_u || !dJ_dnu)
         return fail(SPH_EINVAL, "lam_a, lam_x, lam_u or dJ_dnu is NULL");
+    if (prm->scheme != SPH_SCHEME_SUMMATION)
+        return fail(SPH_EINVAL, "the adjoint covers the summation scheme only");
     return dispatch<RunAccelBackward>(prm, st, lam_a, lam_x, lam_u, dJ_dnu, ws, ws_bytes, stream);
 }
 

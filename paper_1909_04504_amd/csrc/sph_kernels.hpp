@@ -69,7 +69,9 @@ inline void div_magic(uint32_t d, uint32_t* m, int* s1, int* s2) {
     *s2 = l - 1 > 0 ? l - 1 : 0;
 }
 
-// Particle state arrays (device pointers); a, rho, p are of the pair type T.
+// Particle state arrays (device pointers); a and p are of the pair type T,
+// rho too unless rho64 (continuity scheme: rho is integrated, so it is kept
+// in FP64 like x and u).
 struct State {
     double* x[3];
     double* u[3];
@@ -79,7 +81,20 @@ struct State {
     double* m;
     uint8_t* type;
     int32_t* id;
+    int rho64;
 };
+
+template <typename T>
+__device__ __forceinline__ double load_rho(const void* rho, int i, int rho64) {
+    return rho64 ? ((const double*)rho)[i] : (double)((const T*)rho)[i];
+}
+template <typename T>
+__device__ __forceinline__ void store_rho(void* rho, int i, double v, int rho64) {
+    if (rho64)
+        ((double*)rho)[i] = v;
+    else
+        ((T*)rho)[i] = (T)v;
+}
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
@@ -706,13 +721,14 @@ __device__ __forceinline__ void wave_group(uint32_t key, int* leader, int* rank,
 // Opening half kick + drift + periodic wrap of one particle (fluid only;
 // walls keep x and get v = 0), then its cell key and one count for the sort:
 //   v = u + dt/2 a;  x <- wrap(x + dt v);  key = cell(x);  counts[key] += 1.
-// With drift = false only the key and count of the current x.
+// With drift = false only the key and count of the current x; with
+// hash = false only the motion and the domain checks.
 template <int DIM>
 __device__ __forceinline__ void drift_and_hash(int i, const State& S, const Grid& G, bool fluid,
                                                const double* u, const double* a, double hdt,
                                                double dt, bool drift, uint32_t* __restrict__ key,
                                                uint32_t* __restrict__ counts,
-                                               uint32_t* __restrict__ flags) {
+                                               uint32_t* __restrict__ flags, bool hash = true) {
 #pragma clang fp contract(off)
     bool outside = false, nonfinite = false;
     int c[3] = {0, 0, 0};
@@ -737,13 +753,14 @@ __device__ __forceinline__ void drift_and_hash(int i, const State& S, const Grid
         nonfinite |= !isfinite(x);
         c[k] = cell_coord(x, G, k, &outside);
     }
+    if (outside) atomicOr(flags, kFlagOutside);
+    if (nonfinite) atomicOr(flags, kFlagNonFinite);
+    if (!hash) return;
     const uint32_t kk = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
     key[i] = kk;
     int leader = 0, rank = 0, size = 1;
     wave_group(kk, &leader, &rank, &size);
     if (rank == 0) atomicAdd(&counts[kk], (uint32_t)size);
-    if (outside) atomicOr(flags, kFlagOutside);
-    if (nonfinite) atomicOr(flags, kFlagNonFinite);
 }
 
 // Standalone hash (first step of a call, or a plain sort).
@@ -866,7 +883,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int n, const uint32_t* __res
 
 // Stable order inside each cell: slot s holds particle i = tmp[s]; its final
 // slot is start[key] + (number of particles of the same cell with a smaller
-// index).  Gathers the state into that slot and packs the pair records.
+// index).  Gathers the state into that slot and packs the pair records
+// (with eos, also rho and the EOS records of the continuity scheme).
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* __restrict__ tmp,
                                                         const uint32_t* __restrict__ key,
@@ -877,7 +895,10 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
                                                         typename Rec<T>::type* __restrict__ pos,
                                                         typename Vec4<T>::type* __restrict__ vel,
                                                         int copy_derived,
-                                                        uint8_t* __restrict__ type_tape) {
+                                                        uint8_t* __restrict__ type_tape,
+                                                        PairConst<T> C,
+                                                        typename Vec2<T>::type* __restrict__ rp,
+                                                        int eos) {
 #pragma clang fp contract(off)
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
@@ -909,8 +930,20 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
     if (type_tape) type_tape[d] = ty;
     dst.id[d] = src.id[i];
     if (copy_derived) {
-        ((T*)dst.rho)[d] = ((const T*)src.rho)[i];
+        store_rho<T>(dst.rho, d, load_rho<T>(src.rho, i, src.rho64), dst.rho64);
         ((T*)dst.p)[d] = ((const T*)src.p)[i];
+    }
+    if (eos) {
+        // density is a state (continuity scheme): gather it, and the EOS
+        // (eq. eos) gives p and P = p / rho^2, in FP64 as in the density pass
+        const double rho = load_rho<T>(src.rho, i, src.rho64);
+        const double p = tait64<T>(rho, C);
+        store_rho<T>(dst.rho, d, rho, dst.rho64);
+        ((T*)dst.p)[d] = (T)p;
+        typename Vec2<T>::type v2;
+        v2.x = (T)rho;
+        v2.y = (T)(p / (rho * rho));
+        rp[d] = v2;
     }
     typename Vec4<T>::type vr;
     vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
@@ -945,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
     pos[i] = make_rec<T>(xs, c, S.m[i], G, DIM);
     vel[i] = vr;
     if (with_rp) {
-        const T rho = ((const T*)S.rho)[i];
+        const T rho = (T)load_rho<T>(S.rho, i, S.rho64);
         const T p = ((const T*)S.p)[i];
         typename Vec2<T>::type v2;
         v2.x = rho;
@@ -959,10 +992,11 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
 // computed in FP64 and rounded to the pair type.
 template <typename T>
 __device__ __forceinline__ void finish_density(int i, double rho, const PairConst<T>& C,
-                                               T* __restrict__ rho_out, T* __restrict__ p_out,
+                                               void* __restrict__ rho_out, int rho64,
+                                               T* __restrict__ p_out,
                                                typename Vec2<T>::type* __restrict__ rp,
                                                int with_eos) {
-    rho_out[i] = (T)rho;
+    store_rho<T>(rho_out, i, rho, rho64);
     if (with_eos) {
         const double p = tait64<T>(rho, C);
         p_out[i] = (T)p;
@@ -1287,8 +1321,8 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
                                                     const uint32_t* __restrict__ cend,
                                                     const uint32_t* __restrict__ list,
                                                     const uint32_t* __restrict__ ncnt,
-                                                    uint32_t cap, T* __restrict__ rho_out,
-                                                    T* __restrict__ p_out,
+                                                    uint32_t cap, void* __restrict__ rho_out,
+                                                    int rho64, T* __restrict__ p_out,
                                                     typename Vec2<T>::type* __restrict__ rp,
                                                     int with_eos, int count_pairs,
                                                     unsigned long long* __restrict__ pairs) {
@@ -1310,7 +1344,7 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
                                                  kernel_w<KERNEL, double>(q, C.sigma_d);
                                           ++cnt;
                                       });
-        finish_density<T>(i, acc, C, rho_out, p_out, rp, with_eos);
+        finish_density<T>(i, acc, C, rho_out, rho64, p_out, rp, with_eos);
     }
     if (!count_pairs) return;
 #pragma unroll
@@ -1413,6 +1447,105 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
     if (diag_part) block_sum4<1 + DIM>(dv, diag_part, blk, gridDim.x);
 }
 
+// The paper's worked example in one pass over the neighbour lists: the
+// density rate (eqn continuity:sph) drho_i/dt = sum_j m_j v_ij . grad_i W_ij
+// of every particle -- over all neighbours of a fluid particle, over the
+// fluid neighbours of a solid one -- and the momentum equation (pressure, the
+// nu term, g) of the fluid ones (walls: a = 0).  With step, then its Euler
+// stage in FP64: u += dt a; x += dt u with the new u (and the periodic wrap);
+// rho += dt drho/dt; walls keep u = 0 and x.  With hash, the new position is
+// hashed and counted for the next sort.  diag_part and count_pairs as in
+// k_momentum and k_density.
+template <int DIM, int SR, int KERNEL, typename T>
+__global__ __launch_bounds__(kBlock) void k_cont_momentum(
+    int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
+    const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
+    const typename Vec2<T>::type* __restrict__ rp, const uint8_t* __restrict__ type,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap, State S,
+    int step, int hash, double dt, uint32_t* __restrict__ key, uint32_t* __restrict__ counts,
+    uint32_t* __restrict__ flags, double* __restrict__ diag_part, int count_pairs,
+    unsigned long long* __restrict__ pairs) {
+    const int blk = xcd_block();
+    const int i = blk * kBlock + threadIdx.x;
+    double dv[1 + DIM];
+    for (int q = 0; q <= DIM; ++q) dv[q] = 0.0;
+    uint32_t cnt = 0;
+    if (i < n) {
+        const bool fluid = type[i] == 0;
+        const typename Rec<T>::type ri = pos[i];
+        const typename Vec4<T>::type vi = vel[i];
+        const typename Vec2<T>::type rpi = rp[i];
+        T ax = C.g[0], ay = C.g[1], az = C.g[2], ar = T(0);
+        struct Pay {
+            typename Vec4<T>::type v;
+            typename Vec2<T>::type rp;
+            uint8_t t;
+        };
+        for_each_neighbor_p<DIM, SR, T>(
+            i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
+            [&](uint32_t j) { return Pay{vel[j], rp[j], type[j]}; },
+            [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
+                // the self pair adds exact zeros (r = 0, v_ii = 0), as in
+                // k_momentum; a wall's terms are formed and not used
+                ++cnt;
+                const T r2 = g.r2;
+                const T F = kernel_f_r2<KERNEL, T>(r2, C);
+                const T mj = rec_mass(rj);
+                const T vx = vi.x - pj.v.x, vy = vi.y - pj.v.y;
+                const T vz = DIM == 3 ? vi.z - pj.v.z : T(0);
+                const T rv = g.d[0] * vx + g.d[1] * vy + (DIM == 3 ? g.d[2] * vz : T(0));
+                if (fluid || pj.t == 0) ar += mj * (F * rv);
+                const T pres = -(rpi.y + pj.rp.y) * F;
+                const T visc = r2 > T(0) ? C.four_nu * F * r2 *
+                                               p_rcp((rpi.x + pj.rp.x) * (r2 + C.eta_h2))
+                                         : T(0);
+                ax += mj * (pres * g.d[0] + visc * vx);
+                ay += mj * (pres * g.d[1] + visc * vy);
+                if (DIM == 3) az += mj * (pres * g.d[2] + visc * vz);
+            });
+        const T acc[3] = {ax, ay, az};
+        double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < DIM; ++k) {
+            a[k] = fluid ? (double)acc[k] : 0.0;
+            ((T*)S.a[k])[i] = (T)a[k];
+        }
+        if (step) {
+#pragma clang fp contract(off)
+            const double rho = load_rho<T>(S.rho, i, S.rho64);
+            store_rho<T>(S.rho, i, rho + dt * (double)ar, S.rho64);
+            for (int k = 0; k < DIM; ++k) u[k] = fluid ? S.u[k][i] + dt * a[k] : 0.0;
+            if (diag_part) {
+                const double m = S.m[i];
+                double u2 = 0.0;
+                for (int k = 0; k < DIM; ++k) {
+                    u2 += u[k] * u[k];
+                    dv[1 + k] = m * u[k];
+                }
+                dv[0] = 0.5 * m * u2;
+            }
+            // x += dt u with the new u: the drift of drift_and_hash with a
+            // zero half kick
+            const double zero[3] = {0.0, 0.0, 0.0};
+            drift_and_hash<DIM>(i, S, G, fluid, u, zero, 0.0, dt, true, key, counts, flags,
+                                hash != 0);
+        }
+    }
+    if (diag_part) block_sum4<1 + DIM>(dv, diag_part, blk, gridDim.x);
+    if (!count_pairs) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    __shared__ uint32_t wcnt[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
+        pairs[blk] += t;
+        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
+    }
+}
+
 // Neighbour counts (phase 1) and lists (phase 2) of sph_neighbors.
 template <int DIM, int SR, typename T>
 __global__ __launch_bounds__(kBlock) void k_nbr_count(int n, Grid G, PairConst<T> C,
@@ -1453,11 +1586,11 @@ __global__ __launch_bounds__(kBlock) void k_nbr_fill(int n, Grid G, PairConst<T>
 
 // Tait EOS alone (sph_eos).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_eos(int n, PairConst<T> C, const T* __restrict__ rho,
-                                                T* __restrict__ p) {
+__global__ __launch_bounds__(kBlock) void k_eos(int n, PairConst<T> C, const void* __restrict__ rho,
+                                                int rho64, T* __restrict__ p) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    p[i] = (T)tait64<T>((double)rho[i], C);
+    p[i] = (T)tait64<T>(load_rho<T>(rho, i, rho64), C);
 }
 
 // Fill with a constant (used instead of a memset so the sequence can be
@@ -1492,7 +1625,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_state(int n, State src, State d
     dst.m[i] = src.m[i];
     dst.type[i] = src.type[i];
     dst.id[i] = src.id[i];
-    ((T*)dst.rho)[i] = ((const T*)src.rho)[i];
+    store_rho<T>(dst.rho, i, load_rho<T>(src.rho, i, src.rho64), dst.rho64);
     ((T*)dst.p)[i] = ((const T*)src.p)[i];
 }
 

@@ -17,6 +17,8 @@ geometries; the sizes are the benchmark's):
               with three layers of wall particles, gravity -9.81
   cube256     3D periodic cube, 256^3 lattice jittered by +-0.2 dx, Gaussian
               random velocities with standard deviation 0.1
+  dambreak2d  the paper's worked example: 2D dam break with continuity density
+              (dambreak2d_fine: the same at dx = 0.1/32)
 
 Array layout is SoA: x, u have shape (dim, n) float64; m (n,) float64;
 ptype (n,) uint8 (0 fluid, 1 wall); pid (n,) int32.
@@ -34,6 +36,10 @@ WENDLAND = 1
 QUINTIC = 2
 FLUID = 0
 WALL = 1
+# Schemes: summation density with predictor-corrector (kick-drift-kick)
+# steps, and the paper's worked example (continuity density, Euler stage).
+SUMMATION = 0
+CONTINUITY = 1
 
 
 @dataclasses.dataclass
@@ -51,6 +57,7 @@ class Params:
     hi: Tuple[float, float, float]
     periodic: Tuple[int, int, int]
     cell_div: int = 1      # cells per support radius along an axis
+    scheme: int = SUMMATION
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -63,6 +70,7 @@ class State:
     m: np.ndarray      # (n,) float64
     ptype: np.ndarray  # (n,) uint8
     pid: np.ndarray    # (n,) int32
+    rho: np.ndarray = None  # (n,) float64: initial density (continuity scheme)
 
     @property
     def n(self) -> int:
@@ -70,7 +78,7 @@ class State:
 
     def copy(self) -> "State":
         return State(self.x.copy(), self.u.copy(), self.m.copy(), self.ptype.copy(),
-                     self.pid.copy())
+                     self.pid.copy(), None if self.rho is None else self.rho.copy())
 
 
 @dataclasses.dataclass
@@ -176,6 +184,43 @@ def dam_break_3d(dx: float = 0.4 / 93, hdx: float = 1.3, layers: int = 3,
     return params, state
 
 
+def dam_break_2d(dx: float = 0.1, hdx: float = 1.2, rho0: float = 1000.0, c0: float = 10.0,
+                 dt: float = 2e-4, block=(1.0, 2.0), layers: int = 3, tank=(4.0, 4.0),
+                 kernel: int = CUBIC, cell_div: int = 1) -> Tuple[Params, State]:
+    """The paper's worked example (2D dam break): a block of fluid of
+    block[0] x block[1] lattice points at spacing dx centred at
+    (-1.5 + dx, 1 + dx), in a tank whose interior is [-L/2, L/2] x [0, H]
+    (L, H = tank), with `layers` lattice layers of solid particles outside
+    the floor and both sides (open top).  m = rho0 dx^2, rho = rho0, u = 0,
+    g = (0, -9.81), no viscosity, cubic spline h = hdx dx; continuity scheme
+    with the given fixed dt."""
+    nbx, nby = int(round(block[0] / dx)), int(round(block[1] / dx))
+    cx, cy = -1.5 + dx, 1.0 + dx
+    fx = cx + (np.arange(nbx) - 0.5 * (nbx - 1)) * dx
+    fy = cy + (np.arange(nby) - 0.5 * (nby - 1)) * dx
+    gx, gy = np.meshgrid(fx, fy, indexing="ij")
+    fluid = np.stack([gx.T.reshape(-1), gy.T.reshape(-1)])
+    L, H = tank
+    t = layers * dx
+    cnt = (int(round((L + 2 * t) / dx)), int(round((H + t) / dx)))
+    box = lattice(cnt, dx, (-0.5 * L - t, -t))
+    inside = (box[0] > -0.5 * L) & (box[0] < 0.5 * L) & (box[1] > 0.0)
+    wall = box[:, ~inside]
+    x = np.concatenate([fluid, wall], axis=1)
+    nf, nw = fluid.shape[1], wall.shape[1]
+    n = nf + nw
+    h = hdx * dx
+    R = (3.0 if kernel == QUINTIC else 2.0) * h
+    params = Params(dim=2, kernel=kernel, h=h, rho0=rho0, c0=c0, nu=0.0, eta=0.01, dt=dt,
+                    g=(0.0, -9.81, 0.0), lo=(-0.5 * L - t - R, -t - R, 0.0),
+                    hi=(0.5 * L + t + R, H + R, 0.0), periodic=(0, 0, 0), cell_div=cell_div,
+                    scheme=CONTINUITY)
+    ptype = np.concatenate([np.zeros(nf, np.uint8), np.ones(nw, np.uint8)])
+    state = State(x=x, u=np.zeros_like(x), m=np.full(n, rho0 * dx * dx), ptype=ptype,
+                  pid=np.arange(n, dtype=np.int32), rho=np.full(n, rho0))
+    return params, state
+
+
 def periodic_cube(n_side: int = 256, jitter: float = 0.2, sigma_u: float = 0.1,
                   hdx: float = 1.5, seed: int = 4, cell_div: int = 1) -> Tuple[Params, State]:
     """3D periodic unit cube: jittered lattice, velocities N(0, sigma_u^2) per
@@ -220,6 +265,18 @@ def workload(name: str, **kw) -> Workload:
     if name == "tg32":
         p, s = taylor_green(32, **kw)
         return Workload(name, p, s, 200, "fp64", "2D Taylor-Green 32x32 (adjoint companion)")
+    if name == "dambreak2d":
+        p, s = dam_break_2d(**kw)
+        return Workload(name, p, s, 500, "fp64",
+                        "2D dam break of the paper's worked example: 1 x 2 block in a 4 x 4 "
+                        "tank, dx = 0.1, h = 1.2 dx, continuity density, Euler stage, "
+                        "dt = 2e-4")
+    if name == "dambreak2d_fine":
+        dx = 0.1 / 32
+        p, s = dam_break_2d(dx=dx, dt=2e-4 / 32, **kw)
+        return Workload(name, p, s, 1000, "fp32",
+                        "2D dam break of the paper's worked example at dx = 0.1/32 "
+                        "(320 x 640 block), dt = 2e-4/32")
     if name == "dambreak3d":
         kw.setdefault("cell_div", 2)
         p, s = dam_break_3d(**kw)

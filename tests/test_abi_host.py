@@ -6,6 +6,7 @@ import os
 import re
 
 import pytest
+import torch
 
 import paper_1909_04504_amd as sph
 import sph_workloads as W
@@ -37,8 +38,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # 8 int32 + 6 double + 9 double = 32 + 120 bytes
-    assert ctypes.sizeof(sph.Params) == 8 * 4 + 15 * 8
+    # 8 int32 + 6 double + 9 double + 2 int32 (scheme, reserved)
+    assert ctypes.sizeof(sph.Params) == 8 * 4 + 15 * 8 + 2 * 4
     assert ctypes.sizeof(sph.Particles) == 8 + 9 * 8 + 5 * 8
 
 
@@ -77,7 +78,8 @@ def test_workspace_holds_the_neighbour_lists():
 @pytest.mark.parametrize("field,value", [("dim", 4), ("kernel", 7), ("precision", 3),
                                          ("cell_div", 3), ("h", 0.0), ("h", -1.0),
                                          ("rho0", 0.0), ("c0", 0.0), ("nu", -1.0),
-                                         ("eta", -0.5), ("nbr_cap", 5000)])
+                                         ("eta", -0.5), ("nbr_cap", 5000),
+                                         ("scheme", 2), ("scheme", -1), ("reserved", 1)])
 def test_invalid_params_rejected(field, value):
     prm = _params()
     setattr(prm, field, value)
@@ -141,3 +143,27 @@ def test_entry_points_validate_before_launch():
                            ctypes.byref(tot), ws, 1 << 30, None) == sph.SPH_EINVAL
     # NULL workspace in sph_check
     assert L.sph_check(None, 0, None) == sph.SPH_EINVAL
+
+
+def test_particle_arrays_are_checked_against_the_parameters():
+    """rho is FP64 under the continuity scheme (an integrated state) and of
+    the pair type otherwise; the binding refuses arrays of the other type
+    before anything reaches the library."""
+    p, s = W.dam_break_2d()
+    for prec in (sph.FP64, sph.FP32_MIXED):
+        prm_c = sph.make_params(p, prec)
+        prm_s = sph.make_params(p.replace(scheme=W.SUMMATION), prec)
+        dc = sph.DeviceParticles.from_state(s, prec, device="cpu", scheme=sph.CONTINUITY)
+        ds = sph.DeviceParticles.from_state(s, prec, device="cpu")
+        assert dc.rho.dtype == torch.float64
+        dc.struct(prm_c)
+        ds.struct(prm_s)
+        if prec == sph.FP32_MIXED:
+            with pytest.raises(ValueError):
+                ds.struct(prm_c)
+            with pytest.raises(ValueError):
+                dc.struct(prm_s)
+    with pytest.raises(ValueError):
+        sph.DeviceParticles.from_state(s, sph.FP64, device="cpu").struct(
+            sph.make_params(p, sph.FP32_MIXED))
+    assert (s.rho == p.rho0).all()

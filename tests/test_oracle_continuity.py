@@ -1,0 +1,96 @@
+"""Pins of the oracle's continuity scheme, the paper's worked example: density
+rate by the continuity equation (eqn continuity:sph) over all neighbours of a
+fluid particle and over fluid neighbours of a solid one, the EOS, the momentum
+equation, and the example's Euler stage (u += dt a, then x += dt u with the
+new u, rho += dt drho/dt).
+
+Facts used: a uniform velocity field gives no density rate; a solid that sees
+only solids has none; a linear compression u = -alpha x gives
+drho/dt ~ rho alpha (the continuum rho div u) in the interior; an isolated
+particle under gravity follows the closed form of the Euler recurrence; walls
+stay put and keep rho0 far from the fluid."""
+import numpy as np
+import pytest
+
+import oracle
+import sph_workloads as W
+
+
+def test_uniform_velocity_gives_no_density_rate():
+    p, s = W.dam_break_2d()
+    v = np.empty_like(s.x)
+    v[0], v[1] = 0.75, -0.25
+    arho = oracle.continuity(p, s.x, v, s.m, s.ptype)
+    assert np.all(arho == 0.0)
+
+
+def test_solids_only_see_fluid_sources():
+    """Walls moving against each other but far from the fluid: their rate is
+    exactly zero, while a fluid particle among them would see them."""
+    p, s = W.dam_break_2d()
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=s.x.shape)
+    arho = oracle.continuity(p, s.x, v, s.m, s.ptype)
+    wall = s.ptype == W.WALL
+    fluid_x = s.x[:, ~wall]
+    R = 2 * p.h
+    far = np.array([np.min(np.hypot(*(fluid_x - s.x[:, [i]]))) >= R for i in range(s.n)])
+    sel = wall & far
+    assert sel.sum() > 100
+    assert np.all(arho[sel] == 0.0)
+    s2 = s.copy()
+    s2.ptype[:] = W.FLUID
+    arho2 = oracle.continuity(p, s2.x, v, s2.m, s2.ptype)
+    assert np.count_nonzero(arho2[sel]) > 0.9 * sel.sum()
+
+
+@pytest.mark.parametrize("n_side,tol", [(40, 2e-2), (80, 1e-2)])
+def test_linear_compression_rate(n_side, tol):
+    """u = -alpha x on a lattice: drho/dt ~ rho0 alpha away from the edges."""
+    dx = 1.0 / n_side
+    x = W.lattice((n_side, n_side), dx, (0.0, 0.0))
+    rho0, h = 1000.0, 1.2 * dx
+    p = W.Params(dim=2, kernel=W.CUBIC, h=h, rho0=rho0, c0=10.0, nu=0.0, eta=0.01, dt=1e-4,
+                 g=(0, 0, 0), lo=(-0.1, -0.1, 0), hi=(1.1, 1.1, 0), periodic=(0, 0, 0))
+    alpha = 0.3
+    v = np.zeros_like(x)
+    v[0] = -alpha * x[0]
+    m = np.full(x.shape[1], rho0 * dx * dx)
+    arho = oracle.continuity(p, x, v, m, np.zeros(x.shape[1], np.uint8))
+    inner = np.all((x > 0.2) & (x < 0.8), axis=0)
+    assert np.abs(arho[inner] - rho0 * alpha).max() < tol * rho0 * alpha
+
+
+def test_isolated_particles_follow_the_euler_recurrence():
+    """No neighbours: u_n = u0 + n g dt and, with x updated by the new u,
+    x_n = x0 + n dt u0 + g dt^2 n (n + 1) / 2; rho stays rho0."""
+    x = np.array([[0.1, 0.5, 0.9], [0.2, 0.6, 0.3]])
+    u0 = np.array([[0.5, -0.25, 0.0], [0.0, 0.125, -0.5]])
+    n = x.shape[1]
+    p = W.Params(dim=2, kernel=W.CUBIC, h=0.01, rho0=1000.0, c0=10.0, nu=0.0, eta=0.01,
+                 dt=1e-3, g=(0.0, -9.81, 0.0), lo=(0, 0, 0), hi=(1, 1, 0), periodic=(0, 0, 0),
+                 scheme=W.CONTINUITY)
+    steps = 40
+    out = oracle.step_continuity(p, x, u0, np.full(n, 1000.0), np.full(n, 0.1),
+                                 np.zeros(n, np.uint8), steps)
+    g = np.array([[0.0], [-9.81]])
+    assert np.abs(out["u"] - (u0 + steps * p.dt * g)).max() < 1e-13
+    expect_x = x + steps * p.dt * u0 + g * p.dt ** 2 * steps * (steps + 1) / 2
+    assert np.abs(out["x"] - expect_x).max() < 1e-13
+    assert np.all(out["rho"] == 1000.0)
+
+
+def test_dam_break_walls_stay_and_fluid_falls():
+    wl = W.workload("dambreak2d")
+    p, s = wl.params, wl.state
+    out = oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, 200)
+    wall = s.ptype == W.WALL
+    assert np.array_equal(out["x"][:, wall], s.x[:, wall])
+    assert np.all(out["u"][:, wall] == 0.0)
+    # the column starts to fall: its centre of mass moves down
+    assert out["x"][1, ~wall].mean() < s.x[1, ~wall].mean() - 1e-3
+    # walls beyond the reach of the fluid keep rho0 exactly
+    far = out["x"][1] > 2.5
+    assert np.all(out["rho"][wall & far] == p.rho0)
+    # the EOS of the last evaluation is the Tait law of the then density
+    assert np.all(np.isfinite(out["p"]))
