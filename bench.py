@@ -42,17 +42,23 @@ VALU_PEAK_TFLOPS = 78.6
 FLOPS_PER_PAIR = {
     ("density", 2): 19, ("density", 3): 20,
     ("momentum", 2): 34, ("momentum", 3): 42,
+    # continuity scheme: the momentum pair terms (the viscous one is formed
+    # even at nu = 0) plus v_ij . r_ij (2 dim - 1), its product with the
+    # gradient factor and the mass, and the accumulation
+    ("cont_momentum", 2): 40, ("cont_momentum", 3): 50,
 }
+PAIR_KERNELS = ("nlist", "density", "momentum", "cont_momentum")
+KERNEL_NAMES = {0: "cubic spline", 1: "Wendland C2", 2: "quintic spline"}
 # Neighbour-list build: per candidate pair tested (every particle of the
 # stencil cells of i's cell): the separation (dim), |r|^2 (2 dim - 1).
 FLOPS_PER_TEST = {2: 5, 3: 8}
 
 
-def bytes_per_particle(kernel: str, dim: int, tsize: int) -> int:
+def bytes_per_particle(kernel: str, dim: int, tsize: int, continuity: bool = False) -> int:
     """Algorithmic bytes per particle of each step kernel: every array the
     kernel must touch, read or written once (neighbour re-reads served from
     cache are not algorithmic traffic).  The neighbour lists (4 bytes per
-    interaction) are added per pair by list_bytes()."""
+    interaction) are added per pair by the caller."""
     d, T = dim, tsize
     R = 16 if T == 4 else 32  # pair record: int4 offsets + mass / double4
     if kernel == "nlist":
@@ -64,6 +70,10 @@ def bytes_per_particle(kernel: str, dim: int, tsize: int) -> int:
     if kernel == "momentum":
         # in: record, count, v, (rho, P), type, u (f64); out: a, u (f64), key
         return R + 4 + 4 * T + 2 * T + 1 + 8 * d + d * T + 8 * d + 4
+    if kernel == "cont_momentum":
+        # in: record, count, v, (rho, P), type, u, x, rho (f64);
+        # out: a, u, x, rho (f64), key
+        return R + 4 + 4 * T + 2 * T + 1 + 8 * d + 8 * d + 8 + d * T + 8 * d + 8 * d + 8 + 4
     if kernel == "drift_hash":
         # in: x, u (f64), a, type; out: x, v (f64), key, cell count
         return 16 * d + d * T + 1 + 16 * d + 4 + 4
@@ -71,7 +81,8 @@ def bytes_per_particle(kernel: str, dim: int, tsize: int) -> int:
         # in: slot, key, cell range, state (x, u, m, type, id); out: state, perm, key,
         # pair records (delta, m) and v
         state = 16 * d + 8 + 1 + 4
-        return 4 + 4 + 8 + 2 * state + 4 + 4 + (d + 1) * T + d * T
+        eos = 8 + 8 + T + 2 * T if continuity else 0  # rho in/out, p, (rho, P)
+        return 4 + 4 + 8 + 2 * state + 4 + 4 + (d + 1) * T + d * T + eos
     if kernel == "scatter":
         return 4 + 4 + 4 + 4
     return 0
@@ -104,7 +115,7 @@ def traffic_from_profile(kernel: str, workload: str):
 def run_precision(sph, torch, wl, prec, steps, warmup, timing, nbr_cap=0):
     p, s = wl.params, wl.state
     prm = sph.make_params(p, prec, nbr_cap)
-    dp = sph.DeviceParticles.from_state(s, prec)
+    dp = sph.DeviceParticles.from_state(s, prec, scheme=p.scheme)
     ws = sph.workspace(prm, s.n)
     sph.step(prm, dp, 0, ws, prime=True)
     if warmup:
@@ -183,13 +194,14 @@ def roofline(res, wl, prec, steps, tests=None):
     dim, n = wl.params.dim, wl.state.n
     tsize = 4 if prec == 1 else 8
     inter_per_launch = res["interactions_timed"] / steps
-    nbytes = bytes_per_particle(dom, dim, tsize) * n
-    if dom in ("nlist", "density", "momentum"):
+    nbytes = bytes_per_particle(dom, dim, tsize, wl.params.scheme == 1) * n
+    if dom in PAIR_KERNELS:
         nbytes += 4 * inter_per_launch  # the neighbour lists, written or read once
-    if dom in ("nlist", "density", "momentum"):
+    if dom in PAIR_KERNELS:
         if dom == "nlist":
             flops = FLOPS_PER_TEST[dim] * tests
         else:
+            # the momentum passes do no arithmetic for the self pair
             pairs = inter_per_launch if dom == "density" else inter_per_launch - n
             flops = FLOPS_PER_PAIR[(dom, dim)] * pairs
         intensity = flops / nbytes
@@ -253,10 +265,12 @@ def cpu_baseline(wl, budget_s=15.0):
 
     import oracle
     p, s = wl.params, wl.state
+    if p.scheme == 1:
+        return _cpu_baseline_continuity(wl, budget_s)
     t0 = time.perf_counter()
     st = oracle.step(p, s.x, s.u, s.m, s.ptype, 0, prime=True)
     t_prime = time.perf_counter() - t0
-    nsteps = max(1, int(budget_s / max(t_prime, 1e-3)))
+    nsteps = min(wl.steps, max(1, int(budget_s / max(t_prime, 1e-3))))
     off, _ = oracle.neighbors(p, st["x"])
     t0 = time.perf_counter()
     oracle.step(p, st["x"], st["u"], s.m, s.ptype, nsteps, a=st["a"], prime=False)
@@ -267,6 +281,26 @@ def cpu_baseline(wl, budget_s=15.0):
             "sample": f"{nsteps} of the {wl.steps} steps of {wl.name} ({s.n} particles) from "
                       f"the same initial state, FP64 oracle, 1 thread; interactions counted "
                       f"at the first step's rebuild",
+            "cpu": _cpu_model()}
+
+
+def _cpu_baseline_continuity(wl, budget_s):
+    import oracle
+    p, s = wl.params, wl.state
+    t0 = time.perf_counter()
+    oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, 1)
+    t_one = time.perf_counter() - t0
+    nsteps = min(wl.steps, max(1, int(budget_s / max(t_one, 1e-3))))
+    off, _ = oracle.neighbors(p, s.x)
+    t0 = time.perf_counter()
+    oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
+    dt = time.perf_counter() - t0
+    inter = float(off[-1]) * nsteps
+    return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "ms_per_step": 1e3 * dt / nsteps,
+            "sample": f"{nsteps} of the {wl.steps} steps of {wl.name} ({s.n} particles) from "
+                      f"the initial state, FP64 oracle, 1 thread; interactions counted at "
+                      f"the first step's rebuild",
             "cpu": _cpu_model()}
 
 
@@ -353,9 +387,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 pair terms + f64 integration",
-        "data": "synthetic (seeded jittered lattice, analytic Taylor-Green velocities)",
+        "data": "synthetic (" + wl.description + ")",
         "config": {"workload": wl.name, "description": wl.description, "particles": wl.state.n,
-                   "kernel": "cubic spline", "h_over_dx": 1.3, "rebuild": "every step",
+                   "kernel": KERNEL_NAMES[wl.params.kernel], "h": wl.params.h,
+                   "scheme": ("continuity" if wl.params.scheme == 1 else "summation"),
+                   "cell_div": wl.params.cell_div, "rebuild": "every step",
                    "nbr_cap": args.nbr_cap},
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": rl,

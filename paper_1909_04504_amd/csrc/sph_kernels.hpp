@@ -1058,8 +1058,12 @@ __device__ __forceinline__ float filt_cand(const double4& r, int k, int, int w,
     return (float)((v + (w == 0 ? 0.0 : (w < 0 ? -C.L[k] : C.L[k]))) - centre);
 }
 
-// Neighbour lists of all particles (Sec. 2.2), built cell by cell: one wave
-// per cell (cells_per_wave consecutive cells per wave on very large grids).
+// Neighbour lists of all particles (Sec. 2.2), built cell by cell.  Wave w
+// takes per_wave (<= 64) consecutive cells from w per_wave on (dense grids),
+// or, with by_slots, the cells whose first sorted slot lies in
+// [w per_wave, (w + 1) per_wave): one load of the slots' keys and a ballot of
+// the cell starts name them, so the work follows the particles and empty
+// cells cost nothing however sparse the grid.  Per cell:
 //  * Lane s < number of stencil segments (z row, y row, x piece) loads the
 //    slot range of segment s, and lane t the record of the cell's target t,
 //    all in one round of loads; the loops below read them with readlane.
@@ -1082,8 +1086,8 @@ __device__ __forceinline__ float filt_cand(const double4& r, int k, int, int w,
 // records the number of counters in pairs[-1] so that the reader can sum
 // them.
 template <int DIM, int SR, typename T>
-__global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32_t cells_per_wave,
-                                                  Grid G, PairConst<T> C,
+__global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32_t per_wave,
+                                                  int by_slots, Grid G, PairConst<T> C,
                                                   const uint32_t* __restrict__ skey,
                                                   const typename Rec<T>::type* __restrict__ pos,
                                                   const uint32_t* __restrict__ cstart,
@@ -1100,8 +1104,23 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
     const int lane = (int)(threadIdx.x & 63);
     const int blk = xcd_block();
     const uint64_t wave = (uint64_t)blk * (kBlock / 64) + (threadIdx.x >> 6);
-    const uint64_t c0 = wave * cells_per_wave;
-    const uint64_t c1 = c0 + cells_per_wave < ncells ? c0 + cells_per_wave : ncells;
+    // this wave's cells, one per lane: lane l takes cell w per_wave + l, or
+    // the cell that starts at slot w per_wave + l, if any
+    const uint64_t idx = wave * per_wave + (uint64_t)lane;
+    uint32_t lkey = 0;
+    bool has = false;
+    if ((uint32_t)lane < per_wave) {
+        if (by_slots) {
+            if (idx < (uint64_t)n) {
+                lkey = skey[idx];
+                has = idx == 0 || skey[idx - 1] != lkey;
+            }
+        } else if (idx < (uint64_t)ncells) {
+            lkey = (uint32_t)idx;
+            has = true;
+        }
+    }
+    unsigned long long rest = __ballot(has);
     // stencil position of lane s's segment
     const int sk = lane & 1, syi = (lane >> 1) % NR, szi = (lane >> 1) / NR;
     const int soy = syi - SR, soz = DIM == 3 ? szi - SR : 0;
@@ -1142,10 +1161,22 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
     };
     uint32_t total = 0;
     Ranges cur{}, nxt{};
-    if (c0 < c1) load_ranges((uint32_t)c0, cur);
-    for (uint64_t cu = c0; cu < c1; ++cu) {
-        const uint32_t c = (uint32_t)cu;
-        if (cu + 1 < c1) load_ranges(c + 1, nxt);
+    // each pass consumes one bit of rest, so the loop ends within 64 passes
+    int bit = -1;
+    if (rest) {
+        bit = __ffsll((long long)rest) - 1;
+        rest &= rest - 1ull;
+        load_ranges(__builtin_amdgcn_readlane(lkey, bit), cur);
+    }
+    while (bit >= 0) {
+        const uint32_t c = __builtin_amdgcn_readlane(lkey, bit);
+        int nbit = -1;
+        if (rest) {
+            nbit = __ffsll((long long)rest) - 1;
+            rest &= rest - 1ull;
+            load_ranges(__builtin_amdgcn_readlane(lkey, nbit), nxt);
+        }
+        bit = nbit;
         const uint32_t tb = __builtin_amdgcn_readfirstlane(cur.tb);
         uint32_t te = __builtin_amdgcn_readfirstlane(cur.te);
         te = te < (uint32_t)n ? te : (uint32_t)n;

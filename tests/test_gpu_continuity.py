@@ -180,6 +180,29 @@ def test_continuity_list_capacity_paths(prec):
         assert o["interactions"] == outs[0]["interactions"]
 
 
+@pytest.mark.parametrize("prec", [sph.FP64, sph.FP32_MIXED])
+def test_fine_dam_break_full_size(prec):
+    """The benchmark workload (dam break at dx = 0.1/32, 216,338 particles,
+    a grid with more cells than particles) in the launch configuration the
+    benchmark times: a few steps from the initial state against the oracle,
+    every particle by id."""
+    wl = W.workload("dambreak2d_fine")
+    p, s = wl.params, wl.state
+    rng = np.random.default_rng(24)
+    f = s.ptype == W.FLUID
+    s.u[:, f] = rng.normal(0.0, 0.5, size=(2, int(f.sum())))
+    nsteps = 3
+    ref = _ref(p, s, nsteps)
+    out = _run(p, s, prec, nsteps)
+    if prec == sph.FP64:
+        _compare_fp64(p, out, ref)
+    else:
+        o = order_by_id(out["id"])
+        assert normwise(out["rho"][o], ref["rho"]) < 1e-5
+        assert normwise(out["rho"][o] - p.rho0, ref["rho"] - p.rho0) < 1e-5
+        assert normwise(out["a"][:, o], ref["a"]) < 1e-4
+
+
 def test_adjoint_rejects_continuity():
     p, s = W.dam_break_2d()
     prm = sph.make_params(p, sph.FP64)

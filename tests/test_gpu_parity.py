@@ -41,6 +41,12 @@ def make_case(name):
     if name == "cube3d_quintic":
         p, s = W.periodic_cube(n_side=16, jitter=0.3, sigma_u=0.1, seed=18, hdx=1.0)
         return p.replace(kernel=W.QUINTIC), s
+    if name == "sparse2d":
+        # a small jittered patch in a large non-periodic box: more cells than
+        # particles, so the list build takes its cells from the sorted slots
+        p, s = W.taylor_green(30, jitter=0.3, seed=19)
+        p = p.replace(periodic=(0, 0, 0), lo=(-2.0, -2.0, 0), hi=(3.0, 3.0, 0))
+        return p, s
     if name == "box2d":
         # non-periodic 2D box with gravity, cubic spline
         p, s = W.taylor_green(40, jitter=0.3, seed=16)
@@ -53,7 +59,7 @@ def make_case(name):
 
 
 CASES = ["tg2d", "tg2d_cd2", "cube3d", "cube3d_cd2", "dam3d", "box2d", "tg2d_quintic",
-         "cube3d_quintic"]
+         "cube3d_quintic", "sparse2d"]
 
 
 def gpu_sorted(p, s, prec):
