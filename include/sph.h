@@ -70,11 +70,18 @@ typedef enum {
 typedef enum { SPH_FLUID = 0, SPH_WALL = 1 } sph_particle_type;
 
 /* How sph_step obtains the density (Section 2).  Summation: rho is evaluated
- * from the positions (eq. 2) and stepped with the predictor-corrector scheme.
- * Continuity: rho is a state advanced by the continuity equation
- * (eqn continuity:sph), drho_i/dt = sum_j m_j (u_i - u_j) . gradW_ij, with the
- * Euler stage of the paper's dam-break example (Section 3). */
+ * from the positions (eq. 2).  Continuity: rho is a state advanced by the
+ * continuity equation (eqn continuity:sph),
+ * drho_i/dt = sum_j m_j (u_i - u_j) . gradW_ij. */
 typedef enum { SPH_SCHEME_SUMMATION = 0, SPH_SCHEME_CONTINUITY = 1 } sph_scheme;
+
+/* Time integration of sph_step.  Predictor-corrector: Section 2.1 (both
+ * schemes).  Euler: the stage of the paper's dam-break example (continuity
+ * scheme only). */
+typedef enum {
+    SPH_INTEGRATOR_PREDICTOR_CORRECTOR = 0,
+    SPH_INTEGRATOR_EULER = 1
+} sph_integrator;
 
 /* Run parameters.  gamma of the Tait equation is 7 (Section 2, eq. eos). */
 typedef struct {
@@ -98,8 +105,9 @@ typedef struct {
     double dt;            /* time step, > 0 (sph_step only) */
     double g[3];          /* body acceleration (eq. mom:sph, a_body) */
     double lo[3], hi[3];  /* domain box; the cell grid covers [lo, hi) */
-    int32_t scheme;       /* sph_scheme (sph_step only) */
-    int32_t reserved;     /* must be 0 */
+    int32_t scheme;       /* sph_scheme */
+    int32_t integrator;   /* sph_integrator (sph_step only); EULER needs the
+                           * continuity scheme */
 } sph_params;
 
 /* Particle arrays (device pointers, caller-owned). */
@@ -114,6 +122,9 @@ typedef struct {
     double* m;       /* masses */
     uint8_t* type;   /* sph_particle_type */
     int32_t* id;     /* caller's ids; permuted with the particles */
+    double* arho;    /* drho/dt: required under the continuity scheme (state of
+                      * the predictor-corrector, output of the Euler stage);
+                      * ignored, and may be NULL, otherwise */
 } sph_particles;
 
 /* Cell grid of `prm` (host only).  nc[k] = max(1, floor((hi-lo) cell_div / R))
@@ -175,16 +186,23 @@ int sph_momentum(const sph_params* prm, sph_particles* pa, const uint32_t* cell_
  * diag: NULL, or a device array of nsteps * (1 + dim) doubles receiving after
  * each step the kinetic energy sum m|u|^2/2 and the momentum sum m u.
  *
- * With prm->scheme = SPH_SCHEME_CONTINUITY, pa->rho is an input state (the
- * density of every particle, walls included) and each step is instead:
- * neighbour rebuild at x;  p = EOS(rho) for all particles;
+ * With prm->scheme = SPH_SCHEME_CONTINUITY, pa->rho is a state (the density
+ * of every particle, walls included) and the right-hand side at (x, u, rho)
+ * is: neighbour rebuild at x;  p = EOS(rho) for all particles;
  *   arho_i = sum_{j in N(i)} m_j (u_i - u_j) . gradW_ij  over all j for a
  *   fluid particle and over fluid j for a wall particle;
- *   a_i from the momentum equation for fluid particles (walls: 0);
- * then for fluid particles u <- u + dt a, x <- wrap(x + dt u) (the new u);
- * for every particle rho <- rho + dt arho.  Walls keep x and u = 0.  pa->p
- * and pa->a hold the values of the last step's start; prime_accel is
- * ignored. */
+ *   a_i from the momentum equation for fluid particles (walls: 0).
+ * Walls keep x and u = 0 under both integrators.
+ *   Predictor-corrector: per step, for fluid u and every rho,
+ *     u' = u + dt/2 a;  rho' = rho + dt/2 arho;  x <- wrap(x + dt u');
+ *     rates at the predicted end state (x, u' + dt/2 a, rho' + dt/2 arho);
+ *     u <- u' + dt/2 a;  rho <- rho' + dt/2 arho.
+ *   The rates of a step's end start the next step: prime_accel = 1 first
+ *   evaluates a and arho at the input; 0 takes pa->a and pa->arho as given.
+ *   Euler (prm->integrator = SPH_INTEGRATOR_EULER, the example's stage): per
+ *   step, rates at (x, u, rho), then u <- u + dt a, x <- wrap(x + dt u) with
+ *   the new u, rho <- rho + dt arho; prime_accel is ignored.
+ * pa->p, pa->a and pa->arho hold the last evaluation's values. */
 int sph_step(const sph_params* prm, sph_particles* pa, int64_t nsteps, int prime_accel,
              void* ws, size_t ws_bytes, double* diag, void* stream);
 

@@ -75,6 +75,8 @@ def lib():
         L.orc_adjoint_ke.argtypes = [_P, _i64, _P, _P, _P, _P, _i64, _P, _P, _P]
         L.orc_rollout_ke.argtypes = [_P, _i64, _P, _P, _P, _P, _i64, _P]
         L.orc_step_continuity.argtypes = [_P, _i64, _P, _P, _P, _P, _P, _i64, _P, _P, _P]
+        L.orc_step_continuity_pc.argtypes = [_P, _i64, _P, _P, _P, _P, _P, _i64, _i32, _P, _P,
+                                             _P]
         L.orc_continuity.argtypes = [_P, _i64, _P, _P, _P, _P, _P]
         _lib = L
     return _lib
@@ -242,6 +244,22 @@ def step_continuity(p, x, u, rho, m, ptype, nsteps):
     _check(lib().orc_step_continuity(ctypes.byref(params(p)), n, _ptr(x), _ptr(u), _ptr(rho),
                                      _ptr(m), _ptr(ptype), nsteps, _ptr(pr), _ptr(a),
                                      _ptr(arho)))
+    return dict(x=x, u=u, rho=rho, p=pr, a=a, arho=arho)
+
+
+def step_continuity_pc(p, x, u, rho, m, ptype, nsteps, a=None, arho=None, prime=True):
+    """nsteps of the continuity scheme under the predictor-corrector
+    integration (rho kicked like u).  Returns dict of x, u, rho after the steps
+    and p, a, arho of the last evaluation.  Inputs are not modified."""
+    x, u, rho = (_c(t, np.float64).copy() for t in (x, u, rho))
+    m, ptype = _c(m, np.float64), _c(ptype, np.uint8)
+    n = x.shape[1]
+    a = np.zeros_like(x) if a is None else _c(a, np.float64).copy()
+    arho = np.zeros(n) if arho is None else _c(arho, np.float64).copy()
+    pr = np.zeros(n)
+    _check(lib().orc_step_continuity_pc(ctypes.byref(params(p)), n, _ptr(x), _ptr(u), _ptr(rho),
+                                        _ptr(m), _ptr(ptype), nsteps, 1 if prime else 0,
+                                        _ptr(pr), _ptr(a), _ptr(arho)))
     return dict(x=x, u=u, rho=rho, p=pr, a=a, arho=arho)
 
 

@@ -690,6 +690,60 @@ int orc_step_continuity(const OrcParams* P, int64_t n, double* x, double* u, dou
     return 0;
 }
 
+/* The continuity scheme under the predictor-corrector integration of
+ * Section 2.1, with the density advanced like the velocity (dt/2 kicks of its
+ * rate around the drift), the rates at the step's end being evaluated at the
+ * predicted end state (u* = u' + dt/2 a, rho* = rho' + dt/2 arho) so that
+ * the scheme stays second order (A33):
+ *   u' = u + dt/2 a,  rho' = rho + dt/2 arho   (fluid u; every particle's rho)
+ *   x <- wrap(x + dt u')                        (fluid)
+ *   neighbour rebuild; p = EOS(rho*); arho, a at (x, u*, rho*)
+ *   u <- u' + dt/2 a,  rho <- rho' + dt/2 arho
+ * The rates at a step's end start the next step (first-same-as-last); with
+ * prime they are first evaluated at the input state, else a_io and arho_io
+ * hold them on entry.  Walls keep x and u = 0.  On return a_io, arho_io hold
+ * the last evaluation's rates and p_out its pressure. */
+int orc_step_continuity_pc(const OrcParams* P, int64_t n, double* x, double* u, double* rho,
+                           const double* m, const uint8_t* type, int64_t nsteps, int prime,
+                           double* p_out, double* a_io, double* arho_io) {
+    const int dim = P->dim;
+    const double hdt = 0.5 * P->dt;
+    std::vector<double> p(n), us((size_t)dim * n), rhos(n);
+    auto evaluate = [&](const double* xe, const double* ue, const double* rhoe) -> bool {
+        Nbrs N;
+        if (!neighbours(*P, n, xe, N)) return false;
+        for (int64_t i = 0; i < n; ++i) p[i] = eos(*P, rhoe[i]);
+        continuity(*P, n, xe, ue, m, type, N, arho_io);
+        momentum(*P, n, xe, ue, m, type, rhoe, p.data(), N, a_io);
+        return true;
+    };
+    if (prime && !evaluate(x, u, rho)) return -1;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int64_t i = 0; i < n; ++i) {
+            rho[i] = rho[i] + hdt * arho_io[i];
+            rhos[i] = rho[i] + hdt * arho_io[i];
+            for (int k = 0; k < dim; ++k) {
+                if (type[i] != 0) {
+                    u[k * n + i] = 0.0;
+                    us[k * n + i] = 0.0;
+                    continue;
+                }
+                u[k * n + i] = u[k * n + i] + hdt * a_io[k * n + i];
+                us[k * n + i] = u[k * n + i] + hdt * a_io[k * n + i];
+                x[k * n + i] = wrap(*P, x[k * n + i] + P->dt * u[k * n + i], k);
+            }
+        }
+        if (!evaluate(x, us.data(), rhos.data())) return -1;
+        for (int64_t i = 0; i < n; ++i) {
+            rho[i] = rho[i] + hdt * arho_io[i];
+            for (int k = 0; k < dim; ++k)
+                u[k * n + i] = type[i] != 0 ? 0.0 : u[k * n + i] + hdt * a_io[k * n + i];
+        }
+    }
+    if (p_out && (prime || nsteps > 0)) std::copy(p.begin(), p.end(), p_out);
+    return 0;
+}
+
 /* d rho/dt alone at (x, v) (pins and parity tests). */
 int orc_continuity(const OrcParams* P, int64_t n, const double* x, const double* v,
                    const double* m, const uint8_t* type, double* arho) {

@@ -22,6 +22,7 @@ SPH_OK, SPH_EINVAL, SPH_EWORKSPACE, SPH_ECAPACITY = 0, -1, -2, -3
 SPH_EDOMAIN, SPH_ENONFINITE, SPH_EDEVICE = -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 SUMMATION, CONTINUITY = 0, 1  # sph_params.scheme
+PREDICTOR_CORRECTOR, EULER = 0, 1  # sph_params.integrator
 
 _d = ctypes.c_double
 _i32 = ctypes.c_int32
@@ -40,12 +41,12 @@ class Params(ctypes.Structure):
                 ("periodic", _i32 * 3), ("nbr_cap", _i32),
                 ("h", _d), ("rho0", _d), ("c0", _d), ("nu", _d), ("eta", _d), ("dt", _d),
                 ("g", _d * 3), ("lo", _d * 3), ("hi", _d * 3),
-                ("scheme", _i32), ("reserved", _i32)]
+                ("scheme", _i32), ("integrator", _i32)]
 
 
 class Particles(ctypes.Structure):
     _fields_ = [("n", _i64), ("x", _P * 3), ("u", _P * 3), ("a", _P * 3), ("rho", _P),
-                ("p", _P), ("m", _P), ("type", _P), ("id", _P)]
+                ("p", _P), ("m", _P), ("type", _P), ("id", _P), ("arho", _P)]
 
 
 EXPORTED = ("sph_grid", "sph_workspace_bytes", "sph_bin_sort", "sph_neighbors", "sph_density",
@@ -99,7 +100,7 @@ def make_params(p, precision: int = FP64, nbr_cap: int = 0) -> Params:
         c.g[k], c.lo[k], c.hi[k] = float(p.g[k]), float(p.lo[k]), float(p.hi[k])
     c.nbr_cap = int(nbr_cap)
     c.scheme = int(getattr(p, "scheme", 0))
-    c.reserved = 0
+    c.integrator = int(getattr(p, "integrator", 0))
     c.h, c.rho0, c.c0, c.nu, c.eta, c.dt = p.h, p.rho0, p.c0, p.nu, p.eta, p.dt
     return c
 
@@ -134,6 +135,9 @@ class DeviceParticles:
         self.rho = (torch.zeros(self.n, dtype=TR, device=device) if rho is None else
                     _dev(rho, TR, device))
         self.p = torch.zeros(self.n, dtype=T, device=device)
+        # drho/dt: the continuity scheme's rate (FP64), absent otherwise
+        self.arho = (torch.zeros(self.n, dtype=torch.float64, device=device)
+                     if scheme == CONTINUITY else None)
         self.m = _dev(m, torch.float64, device)
         self.type = _dev(ptype, torch.uint8, device)
         self.id = _dev(pid, torch.int32, device)
@@ -151,7 +155,9 @@ class DeviceParticles:
             T = pair_dtype(prm.precision)
             TR = torch.float64 if prm.scheme == CONTINUITY else T
             if (prm.dim != self.dim or self.a.dtype != T or self.p.dtype != T
-                    or self.rho.dtype != TR):
+                    or self.rho.dtype != TR
+                    or (prm.scheme == CONTINUITY and (self.arho is None or
+                                                     self.arho.dtype != torch.float64))):
                 raise ValueError(
                     f"particle arrays (dim {self.dim}, a {self.a.dtype}, rho "
                     f"{self.rho.dtype}) do not match the parameters (dim {prm.dim}, "
@@ -164,11 +170,15 @@ class DeviceParticles:
             c.a[k] = self.a[k].data_ptr()
         c.rho, c.p = self.rho.data_ptr(), self.p.data_ptr()
         c.m, c.type, c.id = self.m.data_ptr(), self.type.data_ptr(), self.id.data_ptr()
+        c.arho = self.arho.data_ptr() if self.arho is not None else None
         return c
 
     def numpy(self) -> dict:
-        return {k: getattr(self, k).cpu().numpy() for k in
-                ("x", "u", "a", "rho", "p", "m", "type", "id")}
+        out = {k: getattr(self, k).cpu().numpy() for k in
+               ("x", "u", "a", "rho", "p", "m", "type", "id")}
+        if self.arho is not None:
+            out["arho"] = self.arho.cpu().numpy()
+        return out
 
     def clone(self) -> "DeviceParticles":
         o = object.__new__(DeviceParticles)

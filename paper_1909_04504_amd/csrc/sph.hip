@@ -133,7 +133,11 @@ int check_params(const sph_params* p, bool need_dt) {
     if (p->cell_div != 1 && p->cell_div != 2) return fail(SPH_EINVAL, "cell_div must be 1 or 2");
     if (p->scheme != SPH_SCHEME_SUMMATION && p->scheme != SPH_SCHEME_CONTINUITY)
         return fail(SPH_EINVAL, "unknown scheme %d", p->scheme);
-    if (p->reserved != 0) return fail(SPH_EINVAL, "reserved must be 0");
+    if (p->integrator != SPH_INTEGRATOR_PREDICTOR_CORRECTOR &&
+        p->integrator != SPH_INTEGRATOR_EULER)
+        return fail(SPH_EINVAL, "unknown integrator %d", p->integrator);
+    if (p->integrator == SPH_INTEGRATOR_EULER && p->scheme != SPH_SCHEME_CONTINUITY)
+        return fail(SPH_EINVAL, "the Euler stage is defined for the continuity scheme only");
     if (p->nbr_cap > kMaxNbrCap)
         return fail(SPH_EINVAL, "nbr_cap must be at most %d (got %d)", kMaxNbrCap, p->nbr_cap);
     if (!(p->h > 0) || !std::isfinite(p->h)) return fail(SPH_EINVAL, "h must be > 0");
@@ -225,6 +229,8 @@ int check_particles(const sph_params* p, const sph_particles* pa) {
     }
     if (!pa->rho || !pa->p || !pa->m || !pa->type || !pa->id)
         return fail(SPH_EINVAL, "rho, p, m, type or id is NULL");
+    if (p->scheme == SPH_SCHEME_CONTINUITY && !pa->arho)
+        return fail(SPH_EINVAL, "arho is NULL (needed by the continuity scheme)");
     return SPH_OK;
 }
 
@@ -232,7 +238,7 @@ int check_particles(const sph_params* p, const sph_particles* pa) {
 // Workspace layout (all offsets 256-byte aligned)
 
 struct StateOff {
-    size_t x, u, a, m, type, id, rho, p;
+    size_t x, u, a, m, type, id, rho, p, arho;
 };
 
 // One recompute-tape slot: the pair records and sort results of one step.
@@ -304,6 +310,7 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
         so.id = take(4 * N);
         so.rho = take(8 * N);
         so.p = take(T * N);
+        so.arho = p->scheme == SPH_SCHEME_CONTINUITY ? take(8 * N) : 0;
         return so;
     };
     const int64_t longest = (ncells + 1 > n + 1) ? ncells + 1 : n + 1;
@@ -376,6 +383,7 @@ sph::State user_state(const sph_particles* pa, const sph_params* p) {
     s.type = pa->type;
     s.id = pa->id;
     s.rho64 = rho_is_f64(p);
+    s.arho = rho_is_f64(p) ? pa->arho : nullptr;
     return s;
 }
 
@@ -394,6 +402,7 @@ sph::State ws_state(char* ws, const StateOff& L, const sph_params* p, int64_t n)
     s.type = (uint8_t*)(ws + L.type);
     s.id = (int32_t*)(ws + L.id);
     s.rho64 = rho_is_f64(p);
+    s.arho = rho_is_f64(p) ? (double*)(ws + L.arho) : nullptr;
     return s;
 }
 
@@ -535,14 +544,18 @@ struct Engine {
     // hashed: src already holds the drifted positions with keys and counts
     // (from the epilogue of the previous momentum launch).
     // eos: gather rho, and form p and the (rho, p/rho^2) records from it
-    // (continuity scheme).
+    // (continuity scheme); predict: records of u + predict a and the EOS at
+    // rho + predict arho (the predictor-corrector's predicted end state);
+    // kick_rho: the opening drift also kicks rho by dt/2 arho.
     int sort_into(const sph::State& src, const sph::State& dst, bool drift, bool copy_derived,
-                  bool hashed = false, bool eos = false) {
+                  bool hashed = false, bool eos = false, double predict = 0.0,
+                  bool kick_rho = false) {
         const unsigned nb = blocks_for(n);
         using TA = T;
         if (!hashed) {
             launch(K_HASH, sph::k_drift_hash<DIM, TA>, nb, st,
-                n, src, G, 0.5 * prm->dt, prm->dt, drift ? 1 : 0, key(), counts(), flags());
+                n, src, G, 0.5 * prm->dt, prm->dt, drift ? 1 : 0, kick_rho ? 1 : 0, key(),
+                counts(), flags());
             SPH_TRY(launch_check("k_drift_hash"));
         }
         SPH_TRY(scan<uint32_t>(counts(), ncells, start()));
@@ -553,7 +566,7 @@ struct Engine {
         launch(K_RANK_GATHER, sph::k_rank_gather<DIM, T>, nb, st, n, tmp(), key(), start(), src, dst, G,
                                                              perm(), skey(), pos(), vel(),
                                                              copy_derived ? 1 : 0, typetape, C,
-                                                             rp(), eos ? 1 : 0);
+                                                             rp(), eos ? 1 : 0, predict);
         return launch_check("k_rank_gather");
     }
 
@@ -709,35 +722,54 @@ struct Engine {
         return SPH_OK;
     }
 
-    // Continuity scheme (the paper's dam-break example): per step, sort
-    // with rho gathered and p = EOS(rho), lists, then one pass for drho/dt and
-    // a with the Euler stage and the next step's hash in its epilogue.
-    int step_continuity(sph_particles* pa, int64_t nsteps, double* diag_out) {
+    // Continuity scheme: lists, then one pass for drho/dt and a with the
+    // integrator's stage and the next step's hash in its epilogue.
+    int cont_pass(const sph::State& s, bool euler, bool kick, bool drift, double* diag_out) {
+        const unsigned nb = blocks_for(n);
+        double* part = diag_out ? (double*)(ws + L.diag) : nullptr;
+        if (L.cap) SPH_TRY(nlist(start(), start() + 1, true));
+        with_reach([&](auto R) {
+            launch(K_CONT, sph::k_cont_momentum<DIM, decltype(R)::value, KERNEL, T>, nb, st, n, G,
+                   C, skey(), pos(), vel(), rp(), (const uint8_t*)s.type, start(), start() + 1,
+                   list_or_null(), lcnt(), L.cap, s, euler ? 1 : 0, kick ? 1 : 0, drift ? 1 : 0,
+                   prm->dt, key(), counts(), flags(), part, L.cap ? 0 : 1, pairs());
+        });
+        SPH_TRY(launch_check("k_cont_momentum"));
+        if (!diag_out) return SPH_OK;
+        launch(K_DIAG, sph::k_diag_final<DIM>, 1, st, (int)nb, part, diag_out);
+        return launch_check("k_diag_final");
+    }
+
+    // Euler stage (the paper's dam-break example): per step, sort with rho
+    // gathered and p = EOS(rho), then the pass.  Predictor-corrector
+    // (Section 2.1): as sph_step's summation scheme with rho kicked like u and
+    // the rates at a step's end evaluated at the predicted end state.
+    int step_continuity(sph_particles* pa, int64_t nsteps, int prime, double* diag_out) {
         const sph::State user = user_state(pa, prm);
         const sph::State wst = ws_state(ws, L.s1, prm, n);
         sph::State cur = user, nxt = wst;
-        const uint32_t* cs = start();
-        const uint32_t* ce = start() + 1;
-        const unsigned nb = blocks_for(n);
-        double* part = (double*)(ws + L.diag);
+        const bool euler = prm->integrator == SPH_INTEGRATOR_EULER;
+        const double hdt = 0.5 * prm->dt;
         SPH_TRY(zero_counts());
+        bool hashed = false;  // cur already opened and hashed by a fused epilogue
+        if (!euler && prime) {
+            SPH_TRY(sort_into(cur, nxt, false, false, false, true));
+            SPH_TRY(cont_pass(nxt, false, false, nsteps > 0, nullptr));
+            std::swap(cur, nxt);
+            hashed = nsteps > 0;
+        }
         for (int64_t s = 0; s < nsteps; ++s) {
             const bool last = s == nsteps - 1;
             double* dg = diag_out ? diag_out + s * (1 + DIM) : nullptr;
-            SPH_TRY(sort_into(cur, nxt, false, false, s > 0, true));
-            if (L.cap) SPH_TRY(nlist(cs, ce, true));
-            with_reach([&](auto R) {
-                launch(K_CONT, sph::k_cont_momentum<DIM, decltype(R)::value, KERNEL, T>, nb, st, n,
-                       G, C, skey(), pos(), vel(), rp(), (const uint8_t*)nxt.type, cs, ce,
-                       list_or_null(), lcnt(), L.cap, nxt, 1, last ? 0 : 1, prm->dt, key(),
-                       counts(), flags(), dg ? part : nullptr, L.cap ? 0 : 1, pairs());
-            });
-            SPH_TRY(launch_check("k_cont_momentum"));
-            if (dg) {
-                launch(K_DIAG, sph::k_diag_final<DIM>, 1, st, (int)nb, part, dg);
-                SPH_TRY(launch_check("k_diag_final"));
+            if (euler) {
+                SPH_TRY(sort_into(cur, nxt, false, false, s > 0, true));
+                SPH_TRY(cont_pass(nxt, true, false, !last, dg));
+            } else {
+                SPH_TRY(sort_into(cur, nxt, true, false, hashed, true, hdt, true));
+                SPH_TRY(cont_pass(nxt, false, true, !last, dg));
             }
             std::swap(cur, nxt);
+            hashed = !last;
         }
         if (cur.m != user.m) SPH_TRY(copy(cur, user));
         return SPH_OK;
@@ -934,7 +966,7 @@ struct RunStep {
                    size_t wb, double* diag, void* st) {
         Engine<DIM, KERNEL, T> E;
         SPH_TRY(make_engine(p, pa, ws, wb, st, &E));
-        if (p->scheme == SPH_SCHEME_CONTINUITY) return E.step_continuity(pa, nsteps, diag);
+        if (p->scheme == SPH_SCHEME_CONTINUITY) return E.step_continuity(pa, nsteps, prime, diag);
         return E.step(pa, nsteps, prime, diag);
     }
 };

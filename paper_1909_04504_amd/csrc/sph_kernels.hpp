@@ -71,7 +71,7 @@ inline void div_magic(uint32_t d, uint32_t* m, int* s1, int* s2) {
 
 // Particle state arrays (device pointers); a and p are of the pair type T,
 // rho too unless rho64 (continuity scheme: rho is integrated, so it is kept
-// in FP64 like x and u).
+// in FP64 like x and u, and arho holds its rate, else arho is null).
 struct State {
     double* x[3];
     double* u[3];
@@ -81,6 +81,7 @@ struct State {
     double* m;
     uint8_t* type;
     int32_t* id;
+    double* arho;
     int rho64;
 };
 
@@ -764,12 +765,15 @@ __device__ __forceinline__ void drift_and_hash(int i, const State& S, const Grid
 }
 
 // Standalone hash (first step of a call, or a plain sort).
+// kick_rho: the opening half kick of the continuity scheme's density,
+// rho <- rho + dt/2 arho, for every particle.
 template <int DIM, typename TA>
 __global__ __launch_bounds__(kBlock) void k_drift_hash(int n, State S, Grid G, double hdt,
-                                                       double dt, int drift,
+                                                       double dt, int drift, int kick_rho,
                                                        uint32_t* __restrict__ key,
                                                        uint32_t* __restrict__ counts,
                                                        uint32_t* __restrict__ flags) {
+#pragma clang fp contract(off)
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
@@ -778,6 +782,8 @@ __global__ __launch_bounds__(kBlock) void k_drift_hash(int n, State S, Grid G, d
             u[k] = S.u[k][i];
             a[k] = (double)((const TA*)S.a[k])[i];
         }
+    if (drift && kick_rho)
+        store_rho<TA>(S.rho, i, load_rho<TA>(S.rho, i, S.rho64) + hdt * S.arho[i], S.rho64);
     drift_and_hash<DIM>(i, S, G, S.type[i] == 0, u, a, hdt, dt, drift != 0, key, counts, flags);
 }
 
@@ -898,7 +904,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
                                                         uint8_t* __restrict__ type_tape,
                                                         PairConst<T> C,
                                                         typename Vec2<T>::type* __restrict__ rp,
-                                                        int eos) {
+                                                        int eos, double predict) {
 #pragma clang fp contract(off)
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= n) return;
@@ -921,7 +927,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
         dst.u[q][d] = u;
         if (copy_derived) ((T*)dst.a[q])[d] = ((const T*)src.a[q])[i];
         xs[q] = x;
-        vv[q] = (T)u;
+        // with predict, the pair records carry u + predict a (the predicted
+        // end-of-step velocity of the continuity scheme's corrector)
+        vv[q] = predict != 0.0 ? (T)(u + predict * (double)((const T*)src.a[q])[i]) : (T)u;
     }
     const double m = src.m[i];
     dst.m[d] = m;
@@ -932,17 +940,20 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
     if (copy_derived) {
         store_rho<T>(dst.rho, d, load_rho<T>(src.rho, i, src.rho64), dst.rho64);
         ((T*)dst.p)[d] = ((const T*)src.p)[i];
+        if (src.arho && dst.arho) dst.arho[d] = src.arho[i];
     }
     if (eos) {
         // density is a state (continuity scheme): gather it, and the EOS
-        // (eq. eos) gives p and P = p / rho^2, in FP64 as in the density pass
+        // (eq. eos) gives p and P = p / rho^2, in FP64 as in the density pass,
+        // at rho + predict arho (the predicted end-of-step density)
         const double rho = load_rho<T>(src.rho, i, src.rho64);
-        const double p = tait64<T>(rho, C);
+        const double rs = predict != 0.0 ? rho + predict * src.arho[i] : rho;
+        const double p = tait64<T>(rs, C);
         store_rho<T>(dst.rho, d, rho, dst.rho64);
         ((T*)dst.p)[d] = (T)p;
         typename Vec2<T>::type v2;
-        v2.x = (T)rho;
-        v2.y = (T)(p / (rho * rho));
+        v2.x = (T)rs;
+        v2.y = (T)(p / (rs * rs));
         rp[d] = v2;
     }
     typename Vec4<T>::type vr;
@@ -1478,14 +1489,19 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
     if (diag_part) block_sum4<1 + DIM>(dv, diag_part, blk, gridDim.x);
 }
 
-// The paper's worked example in one pass over the neighbour lists: the
-// density rate (eqn continuity:sph) drho_i/dt = sum_j m_j v_ij . grad_i W_ij
-// of every particle -- over all neighbours of a fluid particle, over the
-// fluid neighbours of a solid one -- and the momentum equation (pressure, the
-// nu term, g) of the fluid ones (walls: a = 0).  With step, then its Euler
-// stage in FP64: u += dt a; x += dt u with the new u (and the periodic wrap);
-// rho += dt drho/dt; walls keep u = 0 and x.  With hash, the new position is
-// hashed and counted for the next sort.  diag_part and count_pairs as in
+// The continuity scheme in one pass over the neighbour lists: the density
+// rate (eqn continuity:sph) drho_i/dt = sum_j m_j v_ij . grad_i W_ij of every
+// particle -- over all neighbours of a fluid particle, over the fluid
+// neighbours of a solid one -- and the momentum equation (pressure, the nu
+// term, g) of the fluid ones (walls: a = 0); both are stored (a, arho).  The
+// FP64 epilogue then takes one of two integrators:
+//  * euler (the paper's dam-break example): u += dt a; x += dt u with the new
+//    u (and the periodic wrap); rho += dt arho; with drift, the new position
+//    is hashed and counted for the next sort;
+//  * predictor-corrector (Section 2.1): kick closes the step, u = v + dt/2 a
+//    and rho = rho' + dt/2 arho; drift opens the next, v = u + dt/2 a,
+//    rho' = rho + dt/2 arho, x += dt v, and hashes.
+// Walls keep u = 0 and x.  diag_part (after the step) and count_pairs as in
 // k_momentum and k_density.
 template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_cont_momentum(
@@ -1494,8 +1510,9 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
     const typename Vec2<T>::type* __restrict__ rp, const uint8_t* __restrict__ type,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
     const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap, State S,
-    int step, int hash, double dt, uint32_t* __restrict__ key, uint32_t* __restrict__ counts,
-    uint32_t* __restrict__ flags, double* __restrict__ diag_part, int count_pairs,
+    int euler, int kick, int drift, double dt, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ counts, uint32_t* __restrict__ flags, double* __restrict__ diag_part,
+    int count_pairs,
     unsigned long long* __restrict__ pairs) {
     const int blk = xcd_block();
     const int i = blk * kBlock + threadIdx.x;
@@ -1541,11 +1558,22 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
             a[k] = fluid ? (double)acc[k] : 0.0;
             ((T*)S.a[k])[i] = (T)a[k];
         }
-        if (step) {
+        const double arho = (double)ar;
+        S.arho[i] = arho;
+        {
 #pragma clang fp contract(off)
-            const double rho = load_rho<T>(S.rho, i, S.rho64);
-            store_rho<T>(S.rho, i, rho + dt * (double)ar, S.rho64);
-            for (int k = 0; k < DIM; ++k) u[k] = fluid ? S.u[k][i] + dt * a[k] : 0.0;
+            const double hdt = 0.5 * dt;
+            double rho = load_rho<T>(S.rho, i, S.rho64);
+            if (euler) {
+                rho = rho + dt * arho;
+                for (int k = 0; k < DIM; ++k) u[k] = fluid ? S.u[k][i] + dt * a[k] : 0.0;
+            } else {
+                for (int k = 0; k < DIM; ++k) u[k] = S.u[k][i];
+                if (kick) {
+                    rho = rho + hdt * arho;
+                    for (int k = 0; k < DIM; ++k) u[k] = fluid ? u[k] + hdt * a[k] : 0.0;
+                }
+            }
             if (diag_part) {
                 const double m = S.m[i];
                 double u2 = 0.0;
@@ -1555,11 +1583,22 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
                 }
                 dv[0] = 0.5 * m * u2;
             }
-            // x += dt u with the new u: the drift of drift_and_hash with a
-            // zero half kick
-            const double zero[3] = {0.0, 0.0, 0.0};
-            drift_and_hash<DIM>(i, S, G, fluid, u, zero, 0.0, dt, true, key, counts, flags,
-                                hash != 0);
+            if (euler) {
+                // x += dt u with the new u: the drift of drift_and_hash with a
+                // zero half kick
+                const double zero[3] = {0.0, 0.0, 0.0};
+                drift_and_hash<DIM>(i, S, G, fluid, u, zero, 0.0, dt, true, key, counts, flags,
+                                    drift != 0);
+                store_rho<T>(S.rho, i, rho, S.rho64);
+            } else {
+                if (drift) {
+                    rho = rho + hdt * arho;
+                    drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags);
+                } else if (kick) {
+                    for (int k = 0; k < DIM; ++k) S.u[k][i] = u[k];
+                }
+                if (kick || drift) store_rho<T>(S.rho, i, rho, S.rho64);
+            }
         }
     }
     if (diag_part) block_sum4<1 + DIM>(dv, diag_part, blk, gridDim.x);
@@ -1658,6 +1697,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_state(int n, State src, State d
     dst.id[i] = src.id[i];
     store_rho<T>(dst.rho, i, load_rho<T>(src.rho, i, src.rho64), dst.rho64);
     ((T*)dst.p)[i] = ((const T*)src.p)[i];
+    if (src.arho && dst.arho) dst.arho[i] = src.arho[i];
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,8 @@ geometries; the sizes are the benchmark's):
   cube256     3D periodic cube, 256^3 lattice jittered by +-0.2 dx, Gaussian
               random velocities with standard deviation 0.1
   dambreak2d  the paper's worked example: 2D dam break with continuity density
-              (dambreak2d_fine: the same at dx = 0.1/32)
+              and the example's Euler stage (dambreak2d_fine: the same at
+              dx = 0.1/32; dambreak2d_fine_pc: with predictor-corrector steps)
 
 Array layout is SoA: x, u have shape (dim, n) float64; m (n,) float64;
 ptype (n,) uint8 (0 fluid, 1 wall); pid (n,) int32.
@@ -36,10 +37,13 @@ WENDLAND = 1
 QUINTIC = 2
 FLUID = 0
 WALL = 1
-# Schemes: summation density with predictor-corrector (kick-drift-kick)
-# steps, and the paper's worked example (continuity density, Euler stage).
+# Schemes: summation density, or continuity density (the paper's worked
+# example); integrators: predictor-corrector (kick-drift-kick) steps, or the
+# worked example's Euler stage (continuity only).
 SUMMATION = 0
 CONTINUITY = 1
+PREDICTOR_CORRECTOR = 0
+EULER = 1
 
 
 @dataclasses.dataclass
@@ -58,6 +62,7 @@ class Params:
     periodic: Tuple[int, int, int]
     cell_div: int = 1      # cells per support radius along an axis
     scheme: int = SUMMATION
+    integrator: int = PREDICTOR_CORRECTOR
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -186,14 +191,16 @@ def dam_break_3d(dx: float = 0.4 / 93, hdx: float = 1.3, layers: int = 3,
 
 def dam_break_2d(dx: float = 0.1, hdx: float = 1.2, rho0: float = 1000.0, c0: float = 10.0,
                  dt: float = 2e-4, block=(1.0, 2.0), layers: int = 3, tank=(4.0, 4.0),
-                 kernel: int = CUBIC, cell_div: int = 1) -> Tuple[Params, State]:
+                 kernel: int = CUBIC, cell_div: int = 1,
+                 integrator: int = EULER) -> Tuple[Params, State]:
     """The paper's worked example (2D dam break): a block of fluid of
     block[0] x block[1] lattice points at spacing dx centred at
     (-1.5 + dx, 1 + dx), in a tank whose interior is [-L/2, L/2] x [0, H]
     (L, H = tank), with `layers` lattice layers of solid particles outside
     the floor and both sides (open top).  m = rho0 dx^2, rho = rho0, u = 0,
     g = (0, -9.81), no viscosity, cubic spline h = hdx dx; continuity scheme
-    with the given fixed dt."""
+    with the given fixed dt, and the example's Euler stage unless another
+    integrator is asked for."""
     nbx, nby = int(round(block[0] / dx)), int(round(block[1] / dx))
     cx, cy = -1.5 + dx, 1.0 + dx
     fx = cx + (np.arange(nbx) - 0.5 * (nbx - 1)) * dx
@@ -214,7 +221,7 @@ def dam_break_2d(dx: float = 0.1, hdx: float = 1.2, rho0: float = 1000.0, c0: fl
     params = Params(dim=2, kernel=kernel, h=h, rho0=rho0, c0=c0, nu=0.0, eta=0.01, dt=dt,
                     g=(0.0, -9.81, 0.0), lo=(-0.5 * L - t - R, -t - R, 0.0),
                     hi=(0.5 * L + t + R, H + R, 0.0), periodic=(0, 0, 0), cell_div=cell_div,
-                    scheme=CONTINUITY)
+                    scheme=CONTINUITY, integrator=integrator)
     ptype = np.concatenate([np.zeros(nf, np.uint8), np.ones(nw, np.uint8)])
     state = State(x=x, u=np.zeros_like(x), m=np.full(n, rho0 * dx * dx), ptype=ptype,
                   pid=np.arange(n, dtype=np.int32), rho=np.full(n, rho0))
@@ -277,6 +284,12 @@ def workload(name: str, **kw) -> Workload:
         return Workload(name, p, s, 1000, "fp32",
                         "2D dam break of the paper's worked example at dx = 0.1/32 "
                         "(320 x 640 block), dt = 2e-4/32")
+    if name == "dambreak2d_fine_pc":
+        dx = 0.1 / 32
+        p, s = dam_break_2d(dx=dx, dt=2e-4 / 32, integrator=PREDICTOR_CORRECTOR, **kw)
+        return Workload(name, p, s, 1000, "fp32",
+                        "2D dam break of the paper's worked example at dx = 0.1/32 "
+                        "(320 x 640 block), dt = 2e-4/32, predictor-corrector steps")
     if name == "dambreak3d":
         kw.setdefault("cell_div", 2)
         p, s = dam_break_3d(**kw)

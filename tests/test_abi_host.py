@@ -38,9 +38,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # 8 int32 + 6 double + 9 double + 2 int32 (scheme, reserved)
+    # 8 int32 + 6 double + 9 double + 2 int32 (scheme, integrator)
     assert ctypes.sizeof(sph.Params) == 8 * 4 + 15 * 8 + 2 * 4
-    assert ctypes.sizeof(sph.Particles) == 8 + 9 * 8 + 5 * 8
+    # n, x/u/a (3 pointers each), rho, p, m, type, id, arho
+    assert ctypes.sizeof(sph.Particles) == 8 + 9 * 8 + 6 * 8
 
 
 def _params(**kw):
@@ -79,7 +80,8 @@ def test_workspace_holds_the_neighbour_lists():
                                          ("cell_div", 3), ("h", 0.0), ("h", -1.0),
                                          ("rho0", 0.0), ("c0", 0.0), ("nu", -1.0),
                                          ("eta", -0.5), ("nbr_cap", 5000),
-                                         ("scheme", 2), ("scheme", -1), ("reserved", 1)])
+                                         ("scheme", 2), ("scheme", -1), ("integrator", 2),
+                                         ("integrator", 1)])
 def test_invalid_params_rejected(field, value):
     prm = _params()
     setattr(prm, field, value)
@@ -167,3 +169,19 @@ def test_particle_arrays_are_checked_against_the_parameters():
         sph.DeviceParticles.from_state(s, sph.FP64, device="cpu").struct(
             sph.make_params(p, sph.FP32_MIXED))
     assert (s.rho == p.rho0).all()
+
+
+def test_continuity_needs_arho():
+    """Under the continuity scheme the particle set must carry drho/dt; a
+    NULL arho is refused on the host before any launch."""
+    p, s = W.dam_break_2d()
+    prm = sph.make_params(p, sph.FP64)
+    dp = sph.DeviceParticles.from_state(s, sph.FP64, device="cpu", scheme=sph.CONTINUITY)
+    c = dp.struct(prm)
+    c.arho = None
+    cs = torch.zeros(4, dtype=torch.int32)
+    ws = torch.zeros(256, dtype=torch.uint8)
+    rc = sph.lib().sph_bin_sort(ctypes.byref(prm), ctypes.byref(c), ws.data_ptr(), ws.numel(),
+                                cs.data_ptr(), cs.data_ptr(), None)
+    assert rc == sph.SPH_EINVAL
+    assert b"arho" in sph.lib().sph_last_error()

@@ -1,6 +1,7 @@
-"""GPU parity of the continuity scheme (the paper's 2D dam-break example:
-density by the continuity equation, EOS, momentum with gravity, Euler stage)
-against the FP64 CPU oracle, compared by particle id.
+"""GPU parity of the continuity scheme (density by the continuity equation,
+EOS, momentum with gravity; the paper's 2D dam-break example) under both
+integrators (the example's Euler stage and the predictor-corrector) against
+the FP64 CPU oracle, compared by particle id.
 
 Bars: FP64 state within 1e-12 normwise (max |gpu - ref| / max |ref|), with
 the density's departure from rho0 (the part the scheme computes) held to the
@@ -24,11 +25,14 @@ def _shuffle(s: W.State, seed: int) -> W.State:
                    s.ptype[perm].copy(), s.pid[perm].copy(), rho=s.rho[perm].copy())
 
 
-def _moving_dam(seed: int = 21):
+INTEGRATORS = [W.EULER, W.PREDICTOR_CORRECTOR]
+
+
+def _moving_dam(seed: int = 21, integrator: int = W.EULER):
     """The dam-break example with a random fluid velocity field (walls at
     rest) and a perturbed density, so that every term of the step is live
     from the first step on."""
-    p, s = W.dam_break_2d()
+    p, s = W.dam_break_2d(integrator=integrator)
     rng = np.random.default_rng(seed)
     f = s.ptype == W.FLUID
     s.u[:, f] = rng.normal(0.0, 0.5, size=(2, int(f.sum())))
@@ -36,26 +40,33 @@ def _moving_dam(seed: int = 21):
     return p, s
 
 
-def _periodic_continuity(dim: int, seed: int):
+def _periodic_continuity(dim: int, seed: int, integrator: int):
     """Periodic jittered fluid with the continuity scheme: the Taylor-Green
     vortex in 2D, the random-velocity cube in 3D, rho0 with a perturbation."""
     if dim == 2:
         p, s = W.taylor_green(40, jitter=0.3, seed=seed)
     else:
         p, s = W.periodic_cube(n_side=12, jitter=0.3, sigma_u=0.1, seed=seed)
-    p = p.replace(scheme=W.CONTINUITY)
+    p = p.replace(scheme=W.CONTINUITY, integrator=integrator)
     rng = np.random.default_rng(seed + 100)
     s.rho = p.rho0 * (1.0 + rng.uniform(-1e-3, 1e-3, size=s.n))
     return p, s
 
 
-def _run(p, s, prec, nsteps, nbr_cap=0, diag=False):
+def _run(p, s, prec, nsteps, nbr_cap=0, diag=False, splits=None):
+    """nsteps on the GPU (primed), in one call or in calls of the sizes in
+    splits (the rates carried between calls in a and arho)."""
     prm = sph.make_params(p, prec, nbr_cap)
     dp = sph.DeviceParticles.from_state(s, prec, scheme=sph.CONTINUITY)
     ws = sph.workspace(prm, s.n)
     d = (torch.zeros((nsteps, 1 + p.dim), dtype=torch.float64, device="cuda") if diag
          else None)
-    sph.step(prm, dp, nsteps, ws, prime=False, diag=d)
+    if splits is None:
+        sph.step(prm, dp, nsteps, ws, prime=True, diag=d)
+    else:
+        assert sum(splits) == nsteps and d is None
+        for k, ns in enumerate(splits):
+            sph.step(prm, dp, ns, ws, prime=k == 0)
     sph.check(ws)
     out = dp.numpy()
     if diag:
@@ -67,7 +78,10 @@ def _run(p, s, prec, nsteps, nbr_cap=0, diag=False):
 def _ref(p, s, nsteps):
     """The oracle's steps, returned in id order (the oracle keeps the input
     order; the library leaves the particles sorted by cell)."""
-    r = oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
+    if p.integrator == W.EULER:
+        r = oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
+    else:
+        r = oracle.step_continuity_pc(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
     o = order_by_id(s.pid)
     return {k: v[..., o] for k, v in r.items()}
 
@@ -85,6 +99,7 @@ def _compare_fp64(p, out, ref, tol=1e-12):
         "rho": normwise(out["rho"][o], ref["rho"]),
         "drho": normwise(out["rho"][o] - p.rho0, ref["rho"] - p.rho0),
         "a": normwise(out["a"][:, o], ref["a"]),
+        "arho": normwise(out["arho"][o], ref["arho"]),
     }
     # p is a difference of nearly equal terms: against its scale B
     B = p.rho0 * p.c0 ** 2 / 7
@@ -94,11 +109,12 @@ def _compare_fp64(p, out, ref, tol=1e-12):
         assert v < tol, (k, v)
 
 
+@pytest.mark.parametrize("integrator", INTEGRATORS)
 @pytest.mark.parametrize("nsteps", [1, 100])
-def test_dam_break_trajectory_fp64(nsteps):
+def test_dam_break_trajectory_fp64(nsteps, integrator):
     """The example as stated (fluid at rest, rho = rho0, gravity): nsteps
-    Euler steps, state by id within 1e-12; walls never move."""
-    p, s = W.dam_break_2d()
+    steps, state by id within 1e-12; walls never move."""
+    p, s = W.dam_break_2d(integrator=integrator)
     s = _shuffle(s, 1)
     ref = _ref(p, s, nsteps)
     out = _run(p, s, sph.FP64, nsteps)
@@ -110,12 +126,14 @@ def test_dam_break_trajectory_fp64(nsteps):
     assert np.all(out["u"][:, o][:, wall] == 0.0)
 
 
+@pytest.mark.parametrize("integrator", INTEGRATORS)
 @pytest.mark.parametrize("nsteps", [1, 40])
-def test_moving_dam_trajectory_fp64(nsteps):
+def test_moving_dam_trajectory_fp64(nsteps, integrator):
     """Every term live (random fluid velocities, perturbed density); the
     diagnostics of each step within 1e-12; one step's interaction count is
-    the oracle's sum of neighbour-set sizes."""
-    p, s = _moving_dam()
+    the oracle's sum of neighbour-set sizes (two evaluations, and so twice
+    that, when the predictor-corrector is primed)."""
+    p, s = _moving_dam(integrator=integrator)
     s = _shuffle(s, 2)
     ref = _ref(p, s, nsteps)
     out = _run(p, s, sph.FP64, nsteps, diag=True)
@@ -127,15 +145,16 @@ def test_moving_dam_trajectory_fp64(nsteps):
     mom = ref["u"] @ m
     assert abs(d[0] / ke - 1) < 1e-12
     assert np.abs(d[1:] - mom).max() < 1e-12 * np.abs(mom).max()
-    if nsteps == 1:
+    if nsteps == 1 and integrator == W.EULER:
         ro, _ = oracle.neighbors(p, s.x, brute=True)
         assert out["interactions"] == int(ro[-1])
     assert np.all(out["u"][:, o][:, s.ptype[order_by_id(s.pid)] == W.WALL] == 0.0)
 
 
+@pytest.mark.parametrize("integrator", INTEGRATORS)
 @pytest.mark.parametrize("dim", [2, 3])
-def test_periodic_continuity_fp64(dim):
-    p, s = _periodic_continuity(dim, 31 + dim)
+def test_periodic_continuity_fp64(dim, integrator):
+    p, s = _periodic_continuity(dim, 31 + dim, integrator)
     s = _shuffle(s, 3)
     nsteps = 10
     ref = _ref(p, s, nsteps)
@@ -143,16 +162,17 @@ def test_periodic_continuity_fp64(dim):
     _compare_fp64(p, out, ref)
 
 
+@pytest.mark.parametrize("integrator", INTEGRATORS)
 @pytest.mark.parametrize("case", ["dam", "moving_dam", "periodic2d", "periodic3d"])
-def test_continuity_mixed_precision(case):
+def test_continuity_mixed_precision(case, integrator):
     """FP32 pair terms, FP64 integration: density (and its departure from
     rho0) within 1e-5, acceleration within 1e-4, after a few steps."""
     if case == "dam":
-        p, s = W.dam_break_2d()
+        p, s = W.dam_break_2d(integrator=integrator)
     elif case == "moving_dam":
-        p, s = _moving_dam(22)
+        p, s = _moving_dam(22, integrator)
     else:
-        p, s = _periodic_continuity(2 if case == "periodic2d" else 3, 41)
+        p, s = _periodic_continuity(2 if case == "periodic2d" else 3, 41, integrator)
     nsteps = 5
     ref = _ref(p, s, nsteps)
     out = _run(p, s, sph.FP32_MIXED, nsteps)
@@ -166,27 +186,41 @@ def test_continuity_mixed_precision(case):
     assert e_a < 1e-4
 
 
+@pytest.mark.parametrize("integrator", INTEGRATORS)
 @pytest.mark.parametrize("prec", [sph.FP64, sph.FP32_MIXED])
-def test_continuity_list_capacity_paths(prec):
+def test_continuity_list_capacity_paths(prec, integrator):
     """Lists everywhere, cell walks everywhere and a capacity that sends
     about half the particles to the walk give bitwise the same steps."""
-    p, s = _moving_dam(23)
+    p, s = _moving_dam(23, integrator)
     ro, _ = oracle.neighbors(p, s.x, brute=False)
     split = int(np.median(np.diff(ro)))
     outs = [_run(p, s, prec, 6, cap) for cap in (0, -1, split)]
     for o in outs[1:]:
-        for f in ("x", "u", "a", "rho", "p", "id"):
+        for f in ("x", "u", "a", "rho", "p", "arho", "id"):
             assert np.array_equal(o[f], outs[0][f]), f
         assert o["interactions"] == outs[0]["interactions"]
 
 
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+@pytest.mark.parametrize("prec", [sph.FP64, sph.FP32_MIXED])
+def test_continuity_calls_compose(prec, integrator):
+    """Five steps in one call equal calls of 2 + 1 + 2 steps bitwise: the
+    predictor-corrector carries its rates between calls in a and arho."""
+    p, s = _moving_dam(25, integrator)
+    one = _run(p, s, prec, 5)
+    split = _run(p, s, prec, 5, splits=(2, 1, 2))
+    for f in ("x", "u", "a", "rho", "p", "arho", "id"):
+        assert np.array_equal(split[f], one[f]), f
+
+
 @pytest.mark.parametrize("prec", [sph.FP64, sph.FP32_MIXED])
 def test_fine_dam_break_full_size(prec):
-    """The benchmark workload (dam break at dx = 0.1/32, 216,338 particles,
-    a grid with more cells than particles) in the launch configuration the
+    """The benchmark workloads (dam break at dx = 0.1/32, 216,338 particles,
+    a grid with more cells than particles; Euler stage in FP64,
+    predictor-corrector in mixed precision) in the launch configuration the
     benchmark times: a few steps from the initial state against the oracle,
     every particle by id."""
-    wl = W.workload("dambreak2d_fine")
+    wl = W.workload("dambreak2d_fine" if prec == sph.FP64 else "dambreak2d_fine_pc")
     p, s = wl.params, wl.state
     rng = np.random.default_rng(24)
     f = s.ptype == W.FLUID

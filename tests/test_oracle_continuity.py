@@ -94,3 +94,71 @@ def test_dam_break_walls_stay_and_fluid_falls():
     assert np.all(out["rho"][wall & far] == p.rho0)
     # the EOS of the last evaluation is the Tait law of the then density
     assert np.all(np.isfinite(out["p"]))
+
+
+# ---- the continuity scheme under the predictor-corrector integration ----
+
+def test_pc_isolated_particles_are_exact_under_gravity():
+    """With a constant acceleration the kick-drift-kick recurrence is exact:
+    u_n = u0 + g t_n and x_n = x0 + u0 t_n + g t_n^2 / 2; rho stays rho0."""
+    x = np.array([[0.1, 0.5, 0.9], [0.2, 0.6, 0.3]])
+    u0 = np.array([[0.5, -0.25, 0.0], [0.0, 0.125, -0.5]])
+    n = x.shape[1]
+    p = W.Params(dim=2, kernel=W.CUBIC, h=0.01, rho0=1000.0, c0=10.0, nu=0.0, eta=0.01,
+                 dt=1e-3, g=(0.0, -9.81, 0.0), lo=(0, 0, 0), hi=(1, 1, 0), periodic=(0, 0, 0),
+                 scheme=W.CONTINUITY)
+    steps = 40
+    out = oracle.step_continuity_pc(p, x, u0, np.full(n, 1000.0), np.full(n, 0.1),
+                                    np.zeros(n, np.uint8), steps)
+    g = np.array([[0.0], [-9.81]])
+    t = steps * p.dt
+    assert np.abs(out["u"] - (u0 + g * t)).max() < 1e-13
+    assert np.abs(out["x"] - (x + u0 * t + 0.5 * g * t * t)).max() < 1e-13
+    assert np.all(out["rho"] == 1000.0)
+    assert np.all(out["arho"] == 0.0)
+
+
+def _order_of_convergence(step, p, s, rho, dt0, nsteps0, halvings=2, ref_div=32):
+    """Errors in x at the fixed time nsteps0 dt0 for dt0 / 2^k (k = 0..halvings)
+    against a run at dt0 / ref_div; returns the ratios of successive errors."""
+    def run(div):
+        q = p.replace(dt=dt0 / div)
+        return step(q, s.x, s.u, rho, s.m, s.ptype, nsteps0 * div)
+    ref = run(ref_div)
+    errs = []
+    for k in range(halvings + 1):
+        d = run(2 ** k)["x"] - ref["x"]
+        d -= np.round(d)
+        errs.append(np.abs(d).max())
+    return [errs[k] / errs[k + 1] for k in range(halvings)], errs
+
+
+def test_pc_is_second_order_and_euler_first():
+    """Halving dt divides the position error at a fixed time by ~4 under the
+    predictor-corrector (rho kicked like u) and by ~2 under the Euler stage:
+    a rate taken at the wrong state or a kick in the wrong place drops the
+    former to first order."""
+    p, s = W.taylor_green(16, jitter=0.2, seed=5)
+    p = p.replace(scheme=W.CONTINUITY)
+    rng = np.random.default_rng(6)
+    rho = p.rho0 * (1.0 + rng.uniform(-2e-3, 2e-3, size=s.n))
+    dt0 = 2 * p.dt
+    pc, e_pc = _order_of_convergence(oracle.step_continuity_pc, p, s, rho, dt0, 8)
+    eu, e_eu = _order_of_convergence(oracle.step_continuity, p, s, rho, dt0, 8)
+    assert all(3.3 < r < 4.7 for r in pc), (pc, e_pc)
+    assert all(1.6 < r < 2.5 for r in eu), (eu, e_eu)
+
+
+def test_pc_and_euler_share_their_first_rates():
+    """Both integrators evaluate the same right-hand side: the rates of a
+    primed predictor-corrector call with no steps equal the Euler step's
+    rates at the same state."""
+    p, s = W.dam_break_2d()
+    rng = np.random.default_rng(7)
+    f = s.ptype == W.FLUID
+    s.u[:, f] = rng.normal(0.0, 0.3, size=(2, int(f.sum())))
+    pc = oracle.step_continuity_pc(p, s.x, s.u, s.rho, s.m, s.ptype, 0)
+    eu = oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, 1)
+    assert np.array_equal(pc["a"], eu["a"])
+    assert np.array_equal(pc["arho"], eu["arho"])
+    assert np.array_equal(pc["arho"], oracle.continuity(p, s.x, s.u, s.m, s.ptype))
