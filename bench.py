@@ -287,13 +287,18 @@ def cpu_baseline(wl, budget_s=15.0):
 def _cpu_baseline_continuity(wl, budget_s):
     import oracle
     p, s = wl.params, wl.state
+    def run(nsteps):
+        if p.integrator == 1:  # the example's Euler stage
+            oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
+        else:
+            oracle.step_continuity_pc(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
     t0 = time.perf_counter()
-    oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, 1)
+    run(1)
     t_one = time.perf_counter() - t0
     nsteps = min(wl.steps, max(1, int(budget_s / max(t_one, 1e-3))))
     off, _ = oracle.neighbors(p, s.x)
     t0 = time.perf_counter()
-    oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
+    run(nsteps)
     dt = time.perf_counter() - t0
     inter = float(off[-1]) * nsteps
     return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
