@@ -262,14 +262,18 @@ struct Layout {
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Launch shape of the cell-cooperative list build.  Dense grids (no more
-// cells than particles): consecutive cells per wave, at most 16,384 waves
-// (two per SIMD slot at full occupancy), each wave overlapping the range
-// loads of its next cell with the current one.  Sparse grids (a tank mostly
+// cells than particles): kNlistCells consecutive cells per wave, each wave
+// overlapping the range loads of its next cell with the current one; short
+// waves also finish the list rows they share before those leave L2
+// (measured, 512^2 / 1024^2 / 2048^2 lattices: 1 cell 36.4 / 117 / 489 us,
+// 2 cells 37.5 / 109 / 454, 3 cells 37.5 / 110 / 462, waves capped at 16,384
+// (38 cells each at 2048^2) 39.1 / 135 / 738).  Sparse grids (a tank mostly
 // empty): one wave per kNlistSlots sorted slots, taking the cells that start
 // there, so that empty cells cost nothing (measured on the 2D dam break at
 // dx = 0.1/32, 351k cells for 216k particles: 103 -> 34 us per build; 8, 16,
 // 32, 64 slots: 34.0, 34.3, 35.7, 50.0 us, and 39.6, 38.9, 44.7, 50.1 us on
-// the dense 512^2 lattice, where the cell mapping takes 36.5 us).
+// the dense 512^2 lattice).
+constexpr uint32_t kNlistCells = 2;
 constexpr uint32_t kNlistSlots = 16;
 static_assert(kNlistSlots >= 1 && kNlistSlots <= 64, "one lane per slot");
 struct NlistShape {
@@ -278,12 +282,10 @@ struct NlistShape {
     int by_slots;
 };
 NlistShape nlist_shape(int64_t n, int64_t ncells) {
-    const int64_t max_waves = 16384, per_block = sph::kBlock / 64;
-    int64_t cpw = (ncells + max_waves - 1) / max_waves;
-    if (cpw < 1) cpw = 1;
-    if (ncells <= n && cpw <= 64) {
-        const int64_t waves = (ncells + cpw - 1) / cpw;
-        return {(unsigned)((waves + per_block - 1) / per_block), (uint32_t)cpw, 0};
+    const int64_t per_block = sph::kBlock / 64;
+    if (ncells <= n) {
+        const int64_t waves = (ncells + kNlistCells - 1) / kNlistCells;
+        return {(unsigned)((waves + per_block - 1) / per_block), kNlistCells, 0};
     }
     const int64_t waves = (n + kNlistSlots - 1) / kNlistSlots;
     return {(unsigned)((waves + per_block - 1) / per_block), kNlistSlots, 1};
@@ -429,6 +431,8 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
     }
     C.R2_lo = (float)(R2 * (1.0 - 1e-5));
     C.R2_hi = (float)(R2 * (1.0 + 1e-5));
+    C.R2_mid = (float)R2;
+    C.R2_w = (float)(2e-5 * R2);
     C.h = (T)h;
     C.inv_h = (T)(1.0 / h);
     C.sigma = (T)sigma;

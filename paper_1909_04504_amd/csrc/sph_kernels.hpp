@@ -150,6 +150,7 @@ struct PairConst {
     double fix_scale[3];      // cell size / 2^27: one fixed-point unit
     float fix_scale_f[3];     // the same in FP32
     float R2_lo, R2_hi;       // (2h)^2 (1 -+ 1e-5): FP32 test band, FP64 inside it
+    float R2_mid, R2_w;       // (2h)^2 and 2e-5 (2h)^2: |r2 - mid| < w covers the band
     T sigma_h4;    // sigma / h^4 (adjoint only)
     T b7;          // 7 B / rho0 = dp/drho at rho0 (adjoint only)
 };
@@ -1113,6 +1114,8 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
     constexpr int kSegs = (DIM == 3 ? NR : 1) * NR * 2;
     static_assert(kSegs <= 64, "one lane per stencil segment");
     const int lane = (int)(threadIdx.x & 63);
+    const int wv = (int)(threadIdx.x >> 6);
+    __shared__ float tco[kBlock / 64][DIM][64];
     const int blk = xcd_block();
     const uint64_t wave = (uint64_t)blk * (kBlock / 64) + (threadIdx.x >> 6);
     // this wave's cells, one per lane: lane l takes cell w per_wave + l, or
@@ -1211,6 +1214,11 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
             }
             // with a far target in the group, every pair takes the exact test
             const bool gfar = kFp64 && __ballot(tfar && (uint32_t)lane < nt) != 0ull;
+            // the targets' coordinates, read back by every lane as LDS
+            // broadcasts (the wave's own slice; its LDS accesses stay in order)
+            __builtin_amdgcn_wave_barrier();
+            for (int k = 0; k < DIM; ++k) tco[wv][k][lane] = tf[k];
+            __builtin_amdgcn_wave_barrier();
             uint32_t cntv = 0;  // lane t: count of target g0 + t
             // this lane's candidate in the current chunk and its stencil data
             uint32_t cj = 0;
@@ -1231,10 +1239,11 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
                     cfar |= kFp64 && !(fabsf(cf[k]) < far);
                 }
                 const bool exact_all = valid && (cfar || gfar);
+                // a lane without a candidate is infinitely far from every
+                // target, so neither test below accepts it
+                if (!valid) cf[0] = __builtin_huge_valf();
                 for (uint32_t t = 0; t < nt; ++t) {
-                    auto tcoord = [&](int k) {
-                        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tf[k]), t));
-                    };
+                    auto tcoord = [&](int k) { return tco[wv][k][t]; };
                     const float dx = tcoord(0) - cf[0], dy = tcoord(1) - cf[1];
                     float r2 = dx * dx + dy * dy;
                     if (DIM == 3) {
@@ -1242,9 +1251,12 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
                         r2 += dz * dz;
                     }
                     // accepted lanes: below the band, or inside it (or far) and
-                    // accepted by the exact predicate
-                    bool acc = valid && r2 < C.R2_lo;
-                    const bool band = exact_all || (valid && !(r2 < C.R2_lo) && r2 < C.R2_hi);
+                    // accepted by the exact predicate.  r2 - mid is exact near
+                    // the band (Sterbenz), so |r2 - mid| < w holds on all of
+                    // [R2_lo, R2_hi] and a little beyond, where the exact test
+                    // decides alike.
+                    bool acc = r2 < C.R2_lo;
+                    const bool band = exact_all || fabsf(r2 - C.R2_mid) < C.R2_w;
                     if (__builtin_amdgcn_ballot_w64(band)) {
                         const R ri = rec_bcast<DIM>(tr, (int)t);
                         const Geom<T> gm = pair_geom<DIM>(ri, rj, ox, oy, oz, wx, wy, wz, C);

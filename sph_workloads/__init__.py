@@ -12,6 +12,7 @@ geometries; the sizes are the benchmark's):
   tg64        2D Taylor-Green vortex, 64x64 lattice, periodic unit box
   tg512       2D Taylor-Green vortex, 512x512 lattice jittered by +-0.1 dx
   tg256       2D Taylor-Green vortex, 256x256 lattice (adjoint workload)
+  tg1024, tg2048  the same as tg512 at 1024^2 and 2048^2 (lattice sweep)
   tg32        2D Taylor-Green vortex, 32x32 lattice (adjoint oracle companion)
   dambreak3d  3D column of water (0.4 x 0.4 x 0.8) in a 1.6 x 0.67 x 0.6 tank
               with three layers of wall particles, gravity -9.81
@@ -265,6 +266,14 @@ def workload(name: str, **kw) -> Workload:
         return Workload(name, p, s, 1000, "fp32",
                         "2D Taylor-Green 512x512 lattice jittered +-0.1dx, Re=100, cubic "
                         "h=1.3dx, 1000 steps")
+    if name in ("tg1024", "tg2048"):
+        # the lattice sweep beyond the headline size, where the step has
+        # enough particles to fill the chip
+        k = int(name[2:])
+        p, s = taylor_green(k, jitter=0.1, seed=1, **kw)
+        return Workload(name, p, s, 200, "fp32",
+                        f"2D Taylor-Green {k}x{k} lattice jittered +-0.1dx, Re=100, cubic "
+                        "h=1.3dx, 200 steps")
     if name == "tg256":
         p, s = taylor_green(256, **kw)
         return Workload(name, p, s, 200, "fp32",
