@@ -605,7 +605,7 @@ struct Engine {
         with_reach([&](auto R) {
             launch(K_DENSITY, sph::k_density<DIM, decltype(R)::value, KERNEL, T>, blocks_for(n), st,
                 n, G, C, skey(), pos(), cs, ce, list_or_null(), lcnt(), L.cap, s.rho, s.rho64,
-                (T*)s.p, rp(), with_eos ? 1 : 0, L.cap ? 0 : 1, pairs());
+                (T*)s.p, vel(), rp(), with_eos ? 1 : 0, L.cap ? 0 : 1, pairs());
         });
         return launch_check("k_density");
     }

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
     if (i >= n) return;
     const typename Rec<T>::type ri = pos[i];
     const typename Vec4<T>::type vi = vel[i];
-    const typename Vec2<T>::type rpi = rp[i];
+    const typename Vec2<T>::type rpi = load_rp<DIM, T>(vi, rp, (uint32_t)i);
     const typename Vec4<T>::type li = lhat[i];
     const T h = p_rcp(C.inv_h);
     const T mi = rec_mass(ri);
@@ -115,7 +115,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
     };
     for_each_neighbor_p<DIM, SR, T>(
         i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
-        [&](uint32_t j) { return Pay{vel[j], rp[j], lhat[j]}; },
+        [&](uint32_t j) {
+            const typename Vec4<T>::type v = vel[j];
+            return Pay{v, load_rp<DIM, T>(v, rp, j), lhat[j]};
+        },
         [&](uint32_t j, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
             const T r2 = g.r2;
             const T dx = g.d[0], dy = g.d[1], dz = g.d[2];

@@ -130,6 +130,30 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
+// (rho, P = p / rho^2) records of the pair passes.  In 2D they ride in the
+// unused z, w slots of the velocity record, so a pass gathers two records per
+// neighbour instead of three; in 3D they have an array of their own.
+template <int DIM, typename T>
+__device__ __forceinline__ typename Vec2<T>::type load_rp(
+    const typename Vec4<T>::type& v, const typename Vec2<T>::type* __restrict__ rp, uint32_t i) {
+    if (DIM == 2) {
+        typename Vec2<T>::type r;
+        r.x = v.z;
+        r.y = v.w;
+        return r;
+    }
+    return rp[i];
+}
+template <int DIM, typename T>
+__device__ __forceinline__ void store_rp(typename Vec4<T>::type* __restrict__ vel,
+                                         typename Vec2<T>::type* __restrict__ rp, uint32_t i,
+                                         const typename Vec2<T>::type& r) {
+    if (DIM == 2)
+        reinterpret_cast<typename Vec2<T>::type*>(vel + i)[1] = r;  // the z, w slots
+    else
+        rp[i] = r;
+}
+
 // Constants of the pair terms in the pair precision T.
 template <typename T>
 struct PairConst {
@@ -943,6 +967,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
         ((T*)dst.p)[d] = ((const T*)src.p)[i];
         if (src.arho && dst.arho) dst.arho[d] = src.arho[i];
     }
+    typename Vec2<T>::type v2;
+    v2.x = T(0);
+    v2.y = T(0);
     if (eos) {
         // density is a state (continuity scheme): gather it, and the EOS
         // (eq. eos) gives p and P = p / rho^2, in FP64 as in the density pass,
@@ -952,13 +979,16 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
         const double p = tait64<T>(rs, C);
         store_rho<T>(dst.rho, d, rho, dst.rho64);
         ((T*)dst.p)[d] = (T)p;
-        typename Vec2<T>::type v2;
         v2.x = (T)rs;
         v2.y = (T)(p / (rs * rs));
-        rp[d] = v2;
+        if (DIM == 3) rp[d] = v2;
     }
+    // in 2D the (rho, P) record rides in z, w: zero here unless the EOS
+    // above formed it (the density pass fills it otherwise)
     typename Vec4<T>::type vr;
-    vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
+    vr.x = vv[0]; vr.y = vv[1];
+    vr.z = DIM == 2 ? v2.x : vv[2];
+    vr.w = DIM == 2 ? v2.y : T(0);
     pos[d] = make_rec<T>(xs, c, m, G, DIM);
     vel[d] = vr;
 }
@@ -995,17 +1025,18 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
         typename Vec2<T>::type v2;
         v2.x = rho;
         v2.y = p / (rho * rho);
-        rp[i] = v2;
+        store_rp<DIM, T>(vel, rp, (uint32_t)i, v2);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Density epilogue: store rho and, with_eos, p and (rho, P = p / rho^2),
 // computed in FP64 and rounded to the pair type.
-template <typename T>
+template <int DIM, typename T>
 __device__ __forceinline__ void finish_density(int i, double rho, const PairConst<T>& C,
                                                void* __restrict__ rho_out, int rho64,
                                                T* __restrict__ p_out,
+                                               typename Vec4<T>::type* __restrict__ vel,
                                                typename Vec2<T>::type* __restrict__ rp,
                                                int with_eos) {
     store_rho<T>(rho_out, i, rho, rho64);
@@ -1015,7 +1046,7 @@ __device__ __forceinline__ void finish_density(int i, double rho, const PairCons
         typename Vec2<T>::type v2;
         v2.x = (T)rho;
         v2.y = (T)(p / (rho * rho));
-        rp[i] = v2;
+        store_rp<DIM, T>(vel, rp, (uint32_t)i, v2);
     }
 }
 
@@ -1377,6 +1408,7 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
                                                     const uint32_t* __restrict__ ncnt,
                                                     uint32_t cap, void* __restrict__ rho_out,
                                                     int rho64, T* __restrict__ p_out,
+                                                    typename Vec4<T>::type* __restrict__ vel,
                                                     typename Vec2<T>::type* __restrict__ rp,
                                                     int with_eos, int count_pairs,
                                                     unsigned long long* __restrict__ pairs) {
@@ -1398,7 +1430,7 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
                                                  kernel_w<KERNEL, double>(q, C.sigma_d);
                                           ++cnt;
                                       });
-        finish_density<T>(i, acc, C, rho_out, rho64, p_out, rp, with_eos);
+        finish_density<DIM, T>(i, acc, C, rho_out, rho64, p_out, vel, rp, with_eos);
     }
     if (!count_pairs) return;
 #pragma unroll
@@ -1442,7 +1474,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
         if (fluid) {
             const typename Rec<T>::type ri = pos[i];
             const typename Vec4<T>::type vi = vel[i];
-            const typename Vec2<T>::type rpi = rp[i];
+            const typename Vec2<T>::type rpi = load_rp<DIM, T>(vi, rp, (uint32_t)i);
             T ax = C.g[0], ay = C.g[1], az = C.g[2];
             struct Pay {
                 typename Vec4<T>::type v;
@@ -1450,7 +1482,10 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
             };
             for_each_neighbor_p<DIM, SR, T>(
                 i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
-                [&](uint32_t j) { return Pay{vel[j], rp[j]}; },
+                [&](uint32_t j) {
+                    const typename Vec4<T>::type v = vel[j];
+                    return Pay{v, load_rp<DIM, T>(v, rp, j)};
+                },
                 [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
                     // The self pair (j = i) is not skipped: r = 0 and
                     // v_i - v_i = 0 multiply finite factors (F is finite at
@@ -1535,7 +1570,7 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
         const bool fluid = type[i] == 0;
         const typename Rec<T>::type ri = pos[i];
         const typename Vec4<T>::type vi = vel[i];
-        const typename Vec2<T>::type rpi = rp[i];
+        const typename Vec2<T>::type rpi = load_rp<DIM, T>(vi, rp, (uint32_t)i);
         T ax = C.g[0], ay = C.g[1], az = C.g[2], ar = T(0);
         struct Pay {
             typename Vec4<T>::type v;
@@ -1544,7 +1579,10 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
         };
         for_each_neighbor_p<DIM, SR, T>(
             i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
-            [&](uint32_t j) { return Pay{vel[j], rp[j], type[j]}; },
+            [&](uint32_t j) {
+                const typename Vec4<T>::type v = vel[j];
+                return Pay{v, load_rp<DIM, T>(v, rp, j), type[j]};
+            },
             [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
                 // the self pair adds exact zeros (r = 0, v_ii = 0), as in
                 // k_momentum; a wall's terms are formed and not used
