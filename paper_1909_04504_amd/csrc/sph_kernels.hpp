@@ -389,27 +389,32 @@ __device__ __forceinline__ int frame_coord_fix(double x, int c, const Grid& G, i
 
 template <typename T>
 __device__ __forceinline__ typename Rec<T>::type make_rec(const double* x, const int* c, double m,
-                                                          const Grid& G, int dim);
+                                                          int type, const Grid& G, int dim);
+// In 2D the z slot carries the particle type (the continuity pass reads it
+// with the record instead of gathering it); every reader of a record's z
+// coordinate is 3D only.
 template <>
 __device__ __forceinline__ double4 make_rec<double>(const double* x, const int*, double m,
-                                                    const Grid&, int dim) {
+                                                    int type, const Grid&, int dim) {
     double4 r;
     r.x = x[0];
     r.y = x[1];
-    r.z = dim == 3 ? x[2] : 0.0;
+    r.z = dim == 3 ? x[2] : (double)type;
     r.w = m;
     return r;
 }
 template <>
-__device__ __forceinline__ int4 make_rec<float>(const double* x, const int* c, double m,
+__device__ __forceinline__ int4 make_rec<float>(const double* x, const int* c, double m, int type,
                                                 const Grid& G, int dim) {
     int4 r;
     r.x = frame_coord_fix(x[0], c[0], G, 0);
     r.y = frame_coord_fix(x[1], c[1], G, 1);
-    r.z = dim == 3 ? frame_coord_fix(x[2], c[2], G, 2) : 0;
+    r.z = dim == 3 ? frame_coord_fix(x[2], c[2], G, 2) : type;
     r.w = __float_as_int((float)m);
     return r;
 }
+__device__ __forceinline__ int rec_type2(const double4& r) { return (int)r.z; }
+__device__ __forceinline__ int rec_type2(const int4& r) { return r.z; }
 
 // Pair geometry for candidate j of particle i.
 //  * FP64: r_ij = fl(x_i - x_j) minus the periodic shift w L of a wrapped
@@ -989,7 +994,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const uint32_t* _
     vr.x = vv[0]; vr.y = vv[1];
     vr.z = DIM == 2 ? v2.x : vv[2];
     vr.w = DIM == 2 ? v2.y : T(0);
-    pos[d] = make_rec<T>(xs, c, m, G, DIM);
+    pos[d] = make_rec<T>(xs, c, m, (int)ty, G, DIM);
     vel[d] = vr;
 }
 
@@ -1017,7 +1022,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
     skey[i] = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
     typename Vec4<T>::type vr;
     vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
-    pos[i] = make_rec<T>(xs, c, S.m[i], G, DIM);
+    pos[i] = make_rec<T>(xs, c, S.m[i], (int)S.type[i], G, DIM);
     vel[i] = vr;
     if (with_rp) {
         const T rho = (T)load_rho<T>(S.rho, i, S.rho64);
@@ -1581,9 +1586,11 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
             i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
             [&](uint32_t j) {
                 const typename Vec4<T>::type v = vel[j];
-                return Pay{v, load_rp<DIM, T>(v, rp, j), type[j]};
+                // 2D: the type rides in the position record
+                return Pay{v, load_rp<DIM, T>(v, rp, j), DIM == 3 ? type[j] : (uint8_t)0};
             },
             [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
+                const int tj = DIM == 3 ? (int)pj.t : rec_type2(rj);
                 // the self pair adds exact zeros (r = 0, v_ii = 0), as in
                 // k_momentum; a wall's terms are formed and not used
                 ++cnt;
@@ -1593,7 +1600,7 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
                 const T vx = vi.x - pj.v.x, vy = vi.y - pj.v.y;
                 const T vz = DIM == 3 ? vi.z - pj.v.z : T(0);
                 const T rv = g.d[0] * vx + g.d[1] * vy + (DIM == 3 ? g.d[2] * vz : T(0));
-                if (fluid || pj.t == 0) ar += mj * (F * rv);
+                if (fluid || tj == 0) ar += mj * (F * rv);
                 const T pres = -(rpi.y + pj.rp.y) * F;
                 const T visc = r2 > T(0) ? C.four_nu * F * r2 *
                                                p_rcp((rpi.x + pj.rp.x) * (r2 + C.eta_h2))
