@@ -316,7 +316,10 @@ Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k
         return so;
     };
     const int64_t longest = (ncells + 1 > n + 1) ? ncells + 1 : n + 1;
-    const size_t nchunks = (size_t)((longest + sph::kScanChunk - 1) / sph::kScanChunk);
+    // chunk sums of the scans: long arrays in chunks of kScanChunk, short
+    // ones in chunks of kBlock * kScanItemsShort (at most 512 of them)
+    const size_t nchunks =
+        std::max<size_t>(512, (size_t)((longest + sph::kScanChunk - 1) / sph::kScanChunk));
     // header (flag word at 0, number of interaction counters at 8), then one
     // 64-bit interaction counter per block of the counting kernel (k_nlist,
     // or k_density without lists) from offset 16
@@ -531,15 +534,23 @@ struct Engine {
         return launch_check("k_fill_u32");
     }
 
-    // exclusive scan of `len` u32 counts into out[0..len]
+    // exclusive scan of `len` u32 counts into out[0..len] (short arrays, e.g.
+    // the cells of a 512^2 lattice, in chunks of 1,024 so that both launches
+    // have several times more blocks)
     template <typename OUT>
     int scan(const uint32_t* in, int64_t len, OUT* out) {
-        const unsigned nch = (unsigned)((len + sph::kScanChunk - 1) / sph::kScanChunk);
+        if (len <= sph::kScanShortMax) return scan_items<OUT, sph::kScanItemsShort>(in, len, out);
+        return scan_items<OUT, sph::kScanItems>(in, len, out);
+    }
+    template <typename OUT, int ITEMS>
+    int scan_items(const uint32_t* in, int64_t len, OUT* out) {
+        constexpr int64_t chunk = (int64_t)sph::kBlock * ITEMS;
+        const unsigned nch = (unsigned)((len + chunk - 1) / chunk);
         {
-        launch(K_CHUNK_SUM, sph::k_chunk_sum, nch, st, in, len, chunks());
+        launch(K_CHUNK_SUM, sph::k_chunk_sum<ITEMS>, nch, st, in, len, chunks());
         SPH_TRY(launch_check("k_chunk_sum"));
         }
-        launch(K_CHUNK_SCAN, sph::k_chunk_scan<OUT>, nch, st, in, len, chunks(), out);
+        launch(K_CHUNK_SCAN, sph::k_chunk_scan<OUT, ITEMS>, nch, st, in, len, chunks(), out);
         return launch_check("k_chunk_scan");
     }
 

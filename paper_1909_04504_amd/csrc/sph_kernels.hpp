@@ -1,9 +1,10 @@
 // Device kernels of the gfx950 WCSPH hot path.
 //
-// Method (arXiv:1909.04504, Section 2): summation density (eq. 2), Tait EOS
-// (eq. eos), momentum with pressure and viscous terms (eqs. mom:sph,
-// mom:sph:press, mom:sph:visc), predictor-corrector integration (Sec. 2.1),
-// uniform-cell neighbour search (Sec. 2.2).
+// Method (arXiv:1909.04504, Section 2): summation density (eq. 2) or the
+// continuity equation (eqn continuity:sph), Tait EOS (eq. eos), momentum with
+// pressure and viscous terms (eqs. mom:sph, mom:sph:press, mom:sph:visc),
+// predictor-corrector integration (Sec. 2.1) or the Euler stage of the
+// paper's dam-break example, uniform-cell neighbour search (Sec. 2.2).
 //
 // Design for CDNA4 (wave64, 256 CUs in 8 XCDs):
 //  * Particles are kept sorted by cell key, so the particles of a stencil row
@@ -14,14 +15,16 @@
 //    per-cell rank (number of smaller previous indices in the same cell)
 //    makes the result identical to a stable sort, hence deterministic.
 //  * Pair records are packed per sorted slot: the position record, the
-//    velocity as a 4-vector and (rho, P = p/rho^2) as a 2-vector.  FP64
+//    velocity as a 4-vector and (rho, P = p/rho^2) as a 2-vector (in 2D
+//    (rho, P) ride in the velocity record and the particle type in the
+//    position record, so a pair pass gathers two records).  FP64
 //    records hold the absolute position; mixed-precision records hold
 //    fixed-point offsets from the centre of the particle's cell, so that a
 //    separation is an exact integer difference.  Either way swapping i and j
 //    negates the separation bitwise and the neighbour predicate (decided in
 //    FP64) is exactly symmetric.
-//  * Each step builds neighbour lists once (one cell walk, or one wave per
-//    cell in 2D) and the density and momentum passes read them densely, in
+//  * Each step builds neighbour lists once (one cell walk, or waves that
+//    take whole cells in 2D) and the pair passes read them densely, in
 //    the walk's order; a particle with more neighbours than the list
 //    capacity is walked instead, with bitwise the same result.
 //  * No floating-point atomics anywhere: every sum is formed by one thread in
@@ -36,8 +39,10 @@
 namespace sph {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
-constexpr int kScanItems = 16;       // items per thread in the scans
+constexpr int kScanItems = 16;       // items per thread in the scans of long arrays
 constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int kScanItemsShort = 4;   // and of arrays of at most kScanShortMax
+constexpr int64_t kScanShortMax = (int64_t)kBlock * kScanItemsShort * 512;
 constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dealt round-robin
 
 enum : uint32_t { kFlagOutside = 1u, kFlagNonFinite = 2u };
@@ -859,13 +864,14 @@ __device__ __forceinline__ V block_exclusive_scan(V v, V* total) {
     return before + incl - v;
 }
 
-// Sum of each chunk of kScanChunk input counts.
+// Sum of each chunk of kBlock * ITEMS input counts.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_chunk_sum(const uint32_t* __restrict__ in, int64_t n,
                                                       uint64_t* __restrict__ sums) {
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * ITEMS) + (int64_t)threadIdx.x * ITEMS;
     uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
+    for (int k = 0; k < ITEMS; ++k)
         if (base + k < n) s += in[base + k];
     uint64_t tot;
     block_exclusive_scan<uint64_t>(s, &tot);
@@ -873,7 +879,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sum(const uint32_t* __restrict
 }
 
 // Exclusive scan of the input counts: out[i] = sum_{k<i} in[k], out[n] = total.
-template <typename OUT>
+template <typename OUT, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_chunk_scan(const uint32_t* __restrict__ in, int64_t n,
                                                        const uint64_t* __restrict__ sums,
                                                        OUT* __restrict__ out) {
@@ -882,18 +888,18 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(const uint32_t* __restric
     for (int c = threadIdx.x; c < (int)blockIdx.x; c += kBlock) off += sums[c];
     uint64_t offtot;
     block_exclusive_scan<uint64_t>(off, &offtot);
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * ITEMS) + (int64_t)threadIdx.x * ITEMS;
+    uint32_t v[ITEMS];
     uint64_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         v[k] = base + k < n ? in[base + k] : 0u;
         s += v[k];
     }
     uint64_t chunk_total;
     uint64_t run = offtot + block_exclusive_scan<uint64_t>(s, &chunk_total);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         if (base + k < n) out[base + k] = (OUT)run;
         run += v[k];
     }
