@@ -248,3 +248,29 @@ def test_adjoint_rejects_continuity():
     with pytest.raises(sph.SphError) as ei:
         sph.step_backward(prm, dp, 1, lam, lam2, dj, ws)
     assert ei.value.code == sph.SPH_EINVAL
+
+
+@pytest.mark.parametrize("prec", [sph.FP64, sph.FP32_MIXED])
+def test_standalone_passes_with_fp64_density(prec):
+    """Under the continuity scheme rho is FP64 in both precisions; the
+    standalone passes read and write it so: summation density, EOS and
+    momentum on a sorted state match the oracle's evaluation."""
+    p, s = _moving_dam(26)
+    prm = sph.make_params(p, prec)
+    dp = sph.DeviceParticles.from_state(s, prec, scheme=sph.CONTINUITY)
+    assert dp.rho.dtype == torch.float64
+    ws = sph.workspace(prm, s.n)
+    cs, ce = sph.cell_arrays(prm)
+    sph.bin_sort(prm, dp, ws, cs, ce)
+    sph.density(prm, dp, cs, ce, ws)
+    sph.eos(prm, dp)
+    sph.momentum(prm, dp, cs, ce, ws)
+    sph.check(ws)
+    out = dp.numpy()
+    rho, pr, a = oracle.evaluate(p, out["x"], out["u"], out["m"], out["type"])
+    tol_rho = 1e-12 if prec == sph.FP64 else 1e-5
+    tol_a = 1e-12 if prec == sph.FP64 else 1e-4
+    assert normwise(out["rho"], rho) < tol_rho
+    B = p.rho0 * p.c0 ** 2 / 7
+    assert np.abs(out["p"] - pr).max() / B < 28 * tol_rho
+    assert normwise(out["a"], a) < tol_a
