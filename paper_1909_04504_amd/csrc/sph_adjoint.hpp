@@ -116,7 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair1(
     for_each_neighbor_p<DIM, SR, T>(
         i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
         [&](uint32_t j) {
-            const typename Vec4<T>::type v = vel[j];
+            typename Vec4<T>::type v = vel[j];
+            keep_whole<DIM>(v);
             return Pay{v, load_rp<DIM, T>(v, rp, j), lhat[j]};
         },
         [&](uint32_t j, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {

@@ -516,6 +516,24 @@ __device__ __forceinline__ size_t list_column(uint32_t i, uint32_t cap) {
     return ((size_t)(i / kListTile) * cap) * kListTile + (size_t)(i % kListTile);
 }
 
+// Keep a gathered 16-byte 2D record whole: with a use of every component
+// the compiler loads it in one 16-byte access instead of narrowing it to the
+// components a pass reads (x, y and w of a 2D position record become two
+// gathers, and a component read only in a branch a third one, issued late).
+// No code.  (Measured on the 512^2 step: momentum 23.5 -> 18.6 us.)  FP64
+// records and 3D ones are left to the compiler: there whole loads only add
+// bytes.
+template <int DIM>
+__device__ __forceinline__ void keep_whole(int4& r) {
+    if (DIM == 2) asm("" : "+v"(r.x), "+v"(r.y), "+v"(r.z), "+v"(r.w));
+}
+template <int DIM>
+__device__ __forceinline__ void keep_whole(float4& r) {
+    if (DIM == 2) asm("" : "+v"(r.x), "+v"(r.y), "+v"(r.z), "+v"(r.w));
+}
+template <int DIM>
+__device__ __forceinline__ void keep_whole(double4&) {}
+
 // No per-candidate payload beyond the position record.
 struct NoPayload {
     __device__ __forceinline__ int operator()(uint32_t) const { return 0; }
@@ -687,7 +705,10 @@ __device__ __forceinline__ void for_each_neighbor_p(
                 cc[u] = q[u] & Code::kMask;
             }
 #pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u) rr[u] = pos[jj[u]];
+            for (uint32_t u = 0; u < kGroup; ++u) {
+                rr[u] = pos[jj[u]];
+                keep_whole<DIM>(rr[u]);
+            }
 #pragma unroll
             for (uint32_t u = 0; u < kGroup; ++u) pp[u] = load(jj[u]);
 #pragma unroll
@@ -704,7 +725,10 @@ __device__ __forceinline__ void for_each_neighbor_p(
 #pragma unroll
             for (uint32_t u = 0; u + 1 < kGroup; ++u) jj[u] = k + u < cnt ? slot(q[u]) : (uint32_t)i;
 #pragma unroll
-            for (uint32_t u = 0; u + 1 < kGroup; ++u) rr[u] = pos[jj[u]];
+            for (uint32_t u = 0; u + 1 < kGroup; ++u) {
+                rr[u] = pos[jj[u]];
+                keep_whole<DIM>(rr[u]);
+            }
 #pragma unroll
             for (uint32_t u = 0; u + 1 < kGroup; ++u) pp[u] = load(jj[u]);
 #pragma unroll
@@ -1494,7 +1518,8 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
             for_each_neighbor_p<DIM, SR, T>(
                 i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
                 [&](uint32_t j) {
-                    const typename Vec4<T>::type v = vel[j];
+                    typename Vec4<T>::type v = vel[j];
+                    keep_whole<DIM>(v);
                     return Pay{v, load_rp<DIM, T>(v, rp, j)};
                 },
                 [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
@@ -1591,7 +1616,8 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
         for_each_neighbor_p<DIM, SR, T>(
             i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
             [&](uint32_t j) {
-                const typename Vec4<T>::type v = vel[j];
+                typename Vec4<T>::type v = vel[j];
+                keep_whole<DIM>(v);
                 // 2D: the type rides in the position record
                 return Pay{v, load_rp<DIM, T>(v, rp, j), DIM == 3 ? type[j] : (uint8_t)0};
             },
