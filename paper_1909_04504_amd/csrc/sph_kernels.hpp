@@ -141,13 +141,17 @@ template <> struct Vec2<double> { using type = double2; };
 template <int DIM, typename T>
 __device__ __forceinline__ typename Vec2<T>::type load_rp(
     const typename Vec4<T>::type& v, const typename Vec2<T>::type* __restrict__ rp, uint32_t i) {
+    typename Vec2<T>::type r;
     if (DIM == 2) {
-        typename Vec2<T>::type r;
         r.x = v.z;
         r.y = v.w;
         return r;
     }
-    return rp[i];
+    r = rp[i];
+    // one load for both: rho alone is read in the viscous term's branch, and
+    // the compiler would otherwise load it there, late, as a gather of its own
+    asm("" : "+v"(r.x), "+v"(r.y));
+    return r;
 }
 template <int DIM, typename T>
 __device__ __forceinline__ void store_rp(typename Vec4<T>::type* __restrict__ vel,
