@@ -469,8 +469,11 @@ __device__ __forceinline__ bool pair_accept(const Geom<double>& g, const PairCon
 }
 __device__ __forceinline__ bool pair_accept(const Geom<float>& g, const PairConst<float>& C) {
     bool acc = g.r2 < C.R2_lo;
-    const bool band = !acc && g.r2 < C.R2_hi;
-    // the FP64 test runs only when some lane of the wave is inside the band
+    // the band, as one compare: r2 - mid is exact near it (Sterbenz), so
+    // |r2 - mid| < w holds on all of [R2_lo, R2_hi] and a little beyond, where
+    // the FP64 test decides alike; that test runs only when some lane of the
+    // wave is inside the band
+    const bool band = fabsf(g.r2 - C.R2_mid) < C.R2_w;
     if (__builtin_amdgcn_ballot_w64(band)) acc = acc || (band && geom_r2d(g, C) < C.R2_d);
     return acc;
 }
