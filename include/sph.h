@@ -76,8 +76,8 @@ typedef enum { SPH_FLUID = 0, SPH_WALL = 1 } sph_particle_type;
 typedef enum { SPH_SCHEME_SUMMATION = 0, SPH_SCHEME_CONTINUITY = 1 } sph_scheme;
 
 /* Time integration of sph_step.  Predictor-corrector: Section 2.1 (both
- * schemes).  Euler: the stage of the paper's dam-break example (continuity
- * scheme only). */
+ * schemes).  Euler: the stage of the paper's dam-break example (Section 3.2,
+ * "An example problem"; continuity scheme only). */
 typedef enum {
     SPH_INTEGRATOR_PREDICTOR_CORRECTOR = 0,
     SPH_INTEGRATOR_EULER = 1

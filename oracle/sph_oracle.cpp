@@ -377,7 +377,7 @@ bool evaluate(const OrcParams& P, int64_t n, const double* x, const double* v, c
     return true;
 }
 
-/* ---- Continuity density: the paper's worked example (its equation
+/* ---- Continuity density: the paper's worked example (Section 3.2; its equation
  * listing and Euler stepper) ----
  * d rho_i / dt = sum_j m_j (v_i - v_j) . gradW_ij (eqn continuity:sph), over
  * every neighbour for fluid destinations and over fluid neighbours only for

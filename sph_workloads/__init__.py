@@ -194,7 +194,7 @@ def dam_break_2d(dx: float = 0.1, hdx: float = 1.2, rho0: float = 1000.0, c0: fl
                  dt: float = 2e-4, block=(1.0, 2.0), layers: int = 3, tank=(4.0, 4.0),
                  kernel: int = CUBIC, cell_div: int = 1,
                  integrator: int = EULER) -> Tuple[Params, State]:
-    """The paper's worked example (2D dam break): a block of fluid of
+    """The paper's worked example (Section 3.2, 2D dam break): a block of fluid of
     block[0] x block[1] lattice points at spacing dx centred at
     (-1.5 + dx, 1 + dx), in a tank whose interior is [-L/2, L/2] x [0, H]
     (L, H = tank), with `layers` lattice layers of solid particles outside
