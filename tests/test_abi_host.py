@@ -185,3 +185,34 @@ def test_continuity_needs_arho():
                                 cs.data_ptr(), cs.data_ptr(), None)
     assert rc == sph.SPH_EINVAL
     assert b"arho" in sph.lib().sph_last_error()
+
+
+def test_binding_layout_matches_the_c_header(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what a
+    C compiler makes of include/sph.h (compiled here with gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    fields = {"sph_params": sph.Params, "sph_particles": sph.Particles}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sph.h"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append(f'    printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.split("\n"):
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, cls in fields.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
