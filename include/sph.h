@@ -2,11 +2,13 @@
  * sph.h -- C ABI of the MI355X (gfx950) weakly-compressible SPH hot path.
  *
  * The method is the one stated in PySPH (arXiv:1909.04504), Section 2 "The SPH
- * method": summation density (eq. 2), the Tait equation of state (eq. eos),
- * the momentum equation with pressure-gradient and viscous terms
- * (eqs. mom:sph, mom:sph:press, mom:sph:visc) and the predictor-corrector
- * time integration (Section 2.1), with neighbours found on a uniform cell grid
- * (Section 2.2, "Nearest neighbor particle search").
+ * method": summation density (eq. 2) or the continuity equation
+ * (eqn continuity:sph), the Tait equation of state (eq. eos), the momentum
+ * equation with pressure-gradient and viscous terms (eqs. mom:sph,
+ * mom:sph:press, mom:sph:visc) and the predictor-corrector time integration
+ * (Section 2.1) -- or the Euler stage of the paper's dam-break example
+ * (Section 3.2) -- with neighbours found on a uniform cell grid (Section 2.2,
+ * "Nearest neighbor particle search").
  *
  * Conventions shared by every entry point
  *   - Memory: every array argument is a DEVICE pointer owned by the caller
