@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_accum(int n, const double* __res
 
 // Fixed-order FP64 sum: per-block partials, then one block adds the total
 // to *out.
-__global__ __launch_bounds__(kBlock) void k_sum_partial(int n, const double* __restrict__ v,
+static __global__ __launch_bounds__(kBlock) void k_sum_partial(int n, const double* __restrict__ v,
                                                         double* __restrict__ part) {
     __shared__ double sh[kBlock];
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_partial(int n, const double* __r
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_sum_accum(int nparts, const double* __restrict__ part,
+static __global__ __launch_bounds__(kBlock) void k_sum_accum(int nparts, const double* __restrict__ part,
                                                       double* __restrict__ out) {
     __shared__ double sh[kBlock];
     double v = 0.0;

@@ -938,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(const uint32_t* __restric
 }
 
 // Scatter particles into their cell's slot range; counts return to zero.
-__global__ __launch_bounds__(kBlock) void k_scatter(int n, const uint32_t* __restrict__ key,
+static __global__ __launch_bounds__(kBlock) void k_scatter(int n, const uint32_t* __restrict__ key,
                                                     const uint32_t* __restrict__ start,
                                                     uint32_t* __restrict__ counts,
                                                     uint32_t* __restrict__ tmp) {
@@ -1761,14 +1761,14 @@ __global__ __launch_bounds__(kBlock) void k_eos(int n, PairConst<T> C, const voi
 
 // Fill with a constant (used instead of a memset so the sequence can be
 // captured into a graph).
-__global__ __launch_bounds__(kBlock) void k_fill_u32(int64_t len, uint32_t v,
+static __global__ __launch_bounds__(kBlock) void k_fill_u32(int64_t len, uint32_t v,
                                                      uint32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < len) out[i] = v;
 }
 
 // cell_start / cell_end from the scanned offsets.
-__global__ __launch_bounds__(kBlock) void k_cell_ranges(int64_t ncells,
+static __global__ __launch_bounds__(kBlock) void k_cell_ranges(int64_t ncells,
                                                         const uint32_t* __restrict__ start,
                                                         uint32_t* __restrict__ cs,
                                                         uint32_t* __restrict__ ce) {
