@@ -192,3 +192,100 @@ def test_subset_evaluation_matches_full():
     r2, p2, a2 = oracle.eval_subset(p, s.x, s.u, s.m, s.ptype, sub)
     assert np.abs(r2 - rho[sub]).max() < 1e-14
     assert np.abs(a2 - a[:, sub]).max() < 1e-12 * np.abs(a).max()
+
+
+def _dense(p, s, rho0):
+    """The same lattice at reference density rho0: m = rho0 dx^d."""
+    p = p.replace(rho0=rho0)
+    s = s.copy()
+    s.m = s.m * rho0
+    return p, s
+
+
+@pytest.mark.parametrize("n_side,tol", [(32, 1.5e-2), (64, 1.5e-2)])
+def test_pressure_term_scales_with_density(n_side, tol):
+    """At rho0 = 1000 (m = rho0 dx^2, the dam-break density) the pressure term
+    still approximates -grad(p)/rho: the p/rho^2 weighting of eq.
+    mom:sph:press and the mass m_j = rho0 dx^2 combine into 1/rho.  A weight
+    p/rho instead of p/rho^2 would be off by a factor rho0."""
+    p, s = _dense(*W.taylor_green(n_side), 1000.0)
+    rho = oracle.density(p, s.x, s.m)
+    assert abs(rho.mean() / 1000.0 - 1) < 1e-3
+    P0 = 500.0
+    pr = P0 * np.sin(2 * np.pi * s.x[0])
+    a = oracle.momentum(p, s.x, np.zeros_like(s.u), s.m, s.ptype, rho, pr)
+    exact = -2 * np.pi * P0 * np.cos(2 * np.pi * s.x[0]) / rho
+    assert np.abs(a[0] - exact).max() < tol * np.abs(exact).max()
+    assert np.abs(a[1]).max() < 1e-9 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("n_side,tol", [(32, 1e-2), (64, 3e-3)])
+def test_viscous_term_independent_of_density(n_side, tol):
+    """At rho0 = 1000 the viscous term is still nu Laplacian(u): the
+    4 nu/(rho_i + rho_j) prefactor of eq. mom:sph:visc cancels the density
+    carried by m_j."""
+    p, s = _dense(*W.taylor_green(n_side), 1000.0)
+    u = np.zeros_like(s.x)
+    u[0] = np.sin(2 * np.pi * s.x[1])
+    rho = oracle.density(p, s.x, s.m)
+    a = oracle.momentum(p, s.x, u, s.m, s.ptype, rho, np.zeros(s.n))
+    exact = -p.nu * (2 * np.pi) ** 2 * u[0]
+    assert np.abs(a[0] - exact).max() < tol * np.abs(exact).max()
+
+
+def _pair(rho, pr, u_i=(0.0, 0.0), nu=0.0, m_j=2.0):
+    """Two particles of a cubic-spline run with h = 1: i at the origin, j at
+    (1, 0) (q = 1), unit mass for i and m_j for j; rho, pr and the velocity
+    of i given; j at rest; no gravity."""
+    p = W.Params(dim=2, kernel=W.CUBIC, h=1.0, rho0=1.0, c0=1.0, nu=nu, eta=0.01, dt=1e-3,
+                 g=(0.0, 0.0, 0.0), lo=(-10.0, -10.0, 0.0), hi=(10.0, 10.0, 0.0),
+                 periodic=(0, 0, 0))
+    x = np.array([[0.0, 1.0], [0.0, 0.0]])
+    v = np.array([[u_i[0], 0.0], [u_i[1], 0.0]])
+    m = np.array([1.0, m_j])
+    a = oracle.momentum(p, x, v, m, np.zeros(2, np.uint8), np.asarray(rho, float),
+                        np.asarray(pr, float))
+    return a[:, 0]
+
+
+def test_pressure_pair_closed_form():
+    """Worked two-particle example of eq. mom:sph:press, by hand: at q = 1 the
+    M4 spline has dW/dr = sigma (-3 + 2.25) / h = -0.75 * 10/(7 pi), and
+    r_ij = x_i - x_j = (-1, 0), so grad_i W_ij = (0.75 * 10/(7 pi), 0).  With
+    p_i = 3, rho_i = 1.5 (P_i = 4/3), p_j = 1, rho_j = 0.5 (P_j = 4), m_j = 2:
+    a_i = -m_j (P_i + P_j) grad_i W_ij = (-80/(7 pi), 0), pointing away from j."""
+    a = _pair([1.5, 0.5], [3.0, 1.0])
+    assert a[0] == pytest.approx(-80.0 / (7.0 * np.pi), rel=1e-14)
+    assert a[1] == 0.0
+
+
+def test_pressure_pair_density_weights():
+    """P = p / rho^2: doubling rho_i divides the force of p_i by exactly 4
+    and leaves that of p_j alone; doubling rho_j does the converse."""
+    base = _pair([1.5, 0.5], [3.0, 0.0])[0]
+    assert _pair([3.0, 0.5], [3.0, 0.0])[0] == pytest.approx(base / 4.0, rel=1e-14)
+    assert _pair([1.5, 1.0], [3.0, 0.0])[0] == pytest.approx(base, rel=1e-14)
+    other = _pair([1.5, 0.5], [0.0, 1.0])[0]
+    assert _pair([1.5, 1.0], [0.0, 1.0])[0] == pytest.approx(other / 4.0, rel=1e-14)
+    assert _pair([3.0, 0.5], [0.0, 1.0])[0] == pytest.approx(other, rel=1e-14)
+    # the two contributions add
+    assert _pair([1.5, 0.5], [3.0, 1.0])[0] == pytest.approx(base + other, rel=1e-14)
+
+
+def test_viscous_pair_closed_form_and_density_sum():
+    """Worked two-particle example of eq. mom:sph:visc, by hand: p = 0, i moves
+    with u_i = (1, 0) towards j at rest, nu = 0.1, eta = 0.01,
+    h = 1, |r| = 1: r_ij . grad_i W_ij = dW/dr |r| = -0.75 * 10/(7 pi), so
+    a_i = m_j 4 nu/(rho_i + rho_j) (-0.75 * 10/(7 pi))/(1 + 0.01) v_ij, a drag
+    against the relative velocity.  The prefactor depends on rho_i + rho_j
+    only: (1, 3), (3, 1) and (2, 2) give the same force."""
+    dwdr = -0.75 * 10.0 / (7.0 * np.pi)
+    expect = 2.0 * 4.0 * 0.1 / 4.0 * dwdr / 1.01
+    for rho in ([1.0, 3.0], [3.0, 1.0], [2.0, 2.0]):
+        a = _pair(rho, [0.0, 0.0], u_i=(1.0, 0.0), nu=0.1)
+        assert a[0] == pytest.approx(expect, rel=1e-14), rho
+        assert a[1] == 0.0
+    # a transverse relative velocity gives a transverse drag of the same size
+    a = _pair([1.0, 3.0], [0.0, 0.0], u_i=(0.0, 1.0), nu=0.1)
+    assert a[0] == 0.0
+    assert a[1] == pytest.approx(expect, rel=1e-14)
