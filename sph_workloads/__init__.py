@@ -194,31 +194,39 @@ def dam_break_2d(dx: float = 0.1, hdx: float = 1.2, rho0: float = 1000.0, c0: fl
                  dt: float = 2e-4, block=(1.0, 2.0), layers: int = 3, tank=(4.0, 4.0),
                  kernel: int = CUBIC, cell_div: int = 1,
                  integrator: int = EULER) -> Tuple[Params, State]:
-    """The paper's worked example (Section 3.2, 2D dam break): a block of fluid of
-    block[0] x block[1] lattice points at spacing dx centred at
-    (-1.5 + dx, 1 + dx), in a tank whose interior is [-L/2, L/2] x [0, H]
-    (L, H = tank), with `layers` lattice layers of solid particles outside
-    the floor and both sides (open top).  m = rho0 dx^2, rho = rho0, u = 0,
-    g = (0, -9.81), no viscosity, cubic spline h = hdx dx; continuity scheme
-    with the given fixed dt, and the example's Euler stage unless another
-    integrator is asked for."""
-    nbx, nby = int(round(block[0] / dx)), int(round(block[1] / dx))
+    """The paper's worked example (Section 3.2, 2D dam break).
+
+    Every particle sits on one lattice of spacing dx through the origin
+    (x = i dx, y = j dx, i and j integers).  Fluid: the lattice points of the
+    block[0] x block[1] rectangle centred at (-1.5 + dx, 1 + dx), edges
+    included, which at dx = 0.1 is the example's 11 x 21 = 231 particles with
+    x from -1.9 to -0.9 (Section 3.2.1 prints both).  Solid: the tank whose
+    interior is -L/2 < x < L/2, y > 0 (L, H = tank), walls up to y = H:
+    `layers` lattice layers on and outside the floor line y = 0 and the side
+    lines x = -+L/2, so the fluid starts one dx from the floor and the left
+    wall.  m = rho0 dx^2, rho = rho0, u = 0, g = (0, -9.81), no viscosity,
+    cubic spline h = hdx dx; continuity scheme with the given fixed dt, and
+    the example's Euler stage unless another integrator is asked for."""
     cx, cy = -1.5 + dx, 1.0 + dx
-    fx = cx + (np.arange(nbx) - 0.5 * (nbx - 1)) * dx
-    fy = cy + (np.arange(nby) - 0.5 * (nby - 1)) * dx
-    gx, gy = np.meshgrid(fx, fy, indexing="ij")
-    fluid = np.stack([gx.T.reshape(-1), gy.T.reshape(-1)])
+    i0 = int(round((cx - 0.5 * block[0]) / dx))
+    j0 = int(round((cy - 0.5 * block[1]) / dx))
+    nbx, nby = int(round(block[0] / dx)) + 1, int(round(block[1] / dx)) + 1
+    gi, gj = np.meshgrid(np.arange(i0, i0 + nbx), np.arange(j0, j0 + nby), indexing="ij")
+    fluid = np.stack([gi.T.reshape(-1) * dx, gj.T.reshape(-1) * dx])
     L, H = tank
-    t = layers * dx
-    cnt = (int(round((L + 2 * t) / dx)), int(round((H + t) / dx)))
-    box = lattice(cnt, dx, (-0.5 * L - t, -t))
-    inside = (box[0] > -0.5 * L) & (box[0] < 0.5 * L) & (box[1] > 0.0)
-    wall = box[:, ~inside]
+    il = int(round(0.5 * L / dx))       # the side lines at i = -+il
+    jt = int(round(H / dx))             # walls up to j = jt
+    wi, wj = np.meshgrid(np.arange(-il - layers + 1, il + layers),
+                         np.arange(-layers + 1, jt + 1), indexing="ij")
+    wi, wj = wi.T.reshape(-1), wj.T.reshape(-1)
+    inside = (wi > -il) & (wi < il) & (wj > 0)
+    wall = np.stack([wi[~inside] * dx, wj[~inside] * dx])
     x = np.concatenate([fluid, wall], axis=1)
     nf, nw = fluid.shape[1], wall.shape[1]
     n = nf + nw
     h = hdx * dx
     R = (3.0 if kernel == QUINTIC else 2.0) * h
+    t = layers * dx
     params = Params(dim=2, kernel=kernel, h=h, rho0=rho0, c0=c0, nu=0.0, eta=0.01, dt=dt,
                     g=(0.0, -9.81, 0.0), lo=(-0.5 * L - t - R, -t - R, 0.0),
                     hi=(0.5 * L + t + R, H + R, 0.0), periodic=(0, 0, 0), cell_div=cell_div,
@@ -284,21 +292,21 @@ def workload(name: str, **kw) -> Workload:
     if name == "dambreak2d":
         p, s = dam_break_2d(**kw)
         return Workload(name, p, s, 500, "fp64",
-                        "2D dam break of the paper's worked example: 1 x 2 block in a 4 x 4 "
-                        "tank, dx = 0.1, h = 1.2 dx, continuity density, Euler stage, "
-                        "dt = 2e-4")
+                        "2D dam break of the paper's worked example: 1 x 2 block (11 x 21 "
+                        "= 231 fluid particles) in a 4 x 4 tank with 3 wall layers, dx = 0.1, "
+                        "h = 1.2 dx, continuity density, Euler stage, dt = 2e-4")
     if name == "dambreak2d_fine":
         dx = 0.1 / 32
         p, s = dam_break_2d(dx=dx, dt=2e-4 / 32, **kw)
         return Workload(name, p, s, 1000, "fp32",
                         "2D dam break of the paper's worked example at dx = 0.1/32 "
-                        "(320 x 640 block), dt = 2e-4/32")
+                        "(321 x 641 block), dt = 2e-4/32")
     if name == "dambreak2d_fine_pc":
         dx = 0.1 / 32
         p, s = dam_break_2d(dx=dx, dt=2e-4 / 32, integrator=PREDICTOR_CORRECTOR, **kw)
         return Workload(name, p, s, 1000, "fp32",
                         "2D dam break of the paper's worked example at dx = 0.1/32 "
-                        "(320 x 640 block), dt = 2e-4/32, predictor-corrector steps")
+                        "(321 x 641 block), dt = 2e-4/32, predictor-corrector steps")
     if name == "dambreak3d":
         kw.setdefault("cell_div", 2)
         p, s = dam_break_3d(**kw)

@@ -162,3 +162,24 @@ def test_pc_and_euler_share_their_first_rates():
     assert np.array_equal(pc["a"], eu["a"])
     assert np.array_equal(pc["arho"], eu["arho"])
     assert np.array_equal(pc["arho"], oracle.continuity(p, s.x, s.u, s.m, s.ptype))
+
+
+def test_dam_break_fixture_is_the_printed_example():
+    """Section 3.2.1 prints the example's fluid block: 231 particles, x from
+    -1.9 to -0.9, density 1000.  The fixture reproduces them (11 x 21 lattice
+    points of spacing 0.1, edges included), on the same lattice as the tank's
+    walls, one dx from the floor and the left wall."""
+    p, s = W.dam_break_2d()
+    fluid = s.ptype == W.FLUID
+    assert int(fluid.sum()) == 231
+    assert s.x[0, fluid].min() == pytest.approx(-1.9, abs=1e-12)
+    assert s.x[0, fluid].max() == pytest.approx(-0.9, abs=1e-12)
+    assert s.x[1, fluid].min() == pytest.approx(0.1, abs=1e-12)
+    assert s.x[1, fluid].max() == pytest.approx(2.1, abs=1e-12)
+    assert np.all(s.rho == 1000.0) and np.all(s.m == pytest.approx(1000.0 * 0.01))
+    assert p.h == pytest.approx(0.12) and p.c0 == 10.0 and p.dt == 2e-4
+    # every particle on the lattice x = i dx, y = j dx
+    assert np.abs(s.x / 0.1 - np.round(s.x / 0.1)).max() < 1e-9
+    wall = ~fluid
+    gap = lambda k, v: np.abs(s.x[k, wall] - v)
+    assert gap(0, -2.0).min() < 1e-12 and gap(1, 0.0).min() < 1e-12
