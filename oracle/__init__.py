@@ -35,8 +35,8 @@ class OrcParams(ctypes.Structure):
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (no contraction, so sums are the plain ones)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC]
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -78,8 +78,17 @@ def lib():
         L.orc_step_continuity_pc.argtypes = [_P, _i64, _P, _P, _P, _P, _P, _i64, _i32, _P, _P,
                                              _P]
         L.orc_continuity.argtypes = [_P, _i64, _P, _P, _P, _P, _P]
+        L.orc_set_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads(1)  # one thread unless asked otherwise
         _lib = L
     return _lib
+
+
+def set_threads(k: int) -> int:
+    """Run the per-destination loops on k OpenMP threads (results are bitwise
+    the same for every k); returns the number in effect."""
+    return int(lib().orc_set_threads(int(k)))
 
 
 def params(p, brute: bool = False) -> OrcParams:

@@ -18,6 +18,13 @@
  *     Computed by brute force O(n^2) or by the paper's uniform cell grid with
  *     the (2s+1)^d stencil; both give the same set (pinned by the tests).
  *
+ * Threads: the per-destination loops (neighbour rows, density, EOS,
+ * momentum, continuity) may run on several OpenMP threads (orc_set_threads);
+ * each destination's sum is still formed by one thread in the same order, so
+ * the results are bitwise those of one thread.  Everything else (the
+ * integrator stages, the diagnostics, the scatter-form adjoint) stays
+ * sequential.  Default: one thread.
+ *
  * Parity status of every function is stated next to it; all are pinned by
  * the CPU tests except where a function says "parity unpinned".
  */
@@ -26,6 +33,8 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+
+#include <omp.h>
 
 extern "C" {
 
@@ -215,17 +224,27 @@ bool in_support(const OrcParams& P, const double* d) {
     return dot(d, d, P.dim) < R * R;
 }
 
-void neighbours_brute(const OrcParams& P, int64_t n, const double* x, Nbrs& N) {
+/* CSR lists from rows formed independently per particle, row_of(i, row). */
+template <typename RowFn>
+void build_rows(int64_t n, Nbrs& N, RowFn&& row_of) {
+    std::vector<std::vector<int64_t>> rows(n);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) row_of(i, rows[i]);
     N.off.assign(n + 1, 0);
-    N.idx.clear();
-    double d[3];
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n; ++i) N.off[i + 1] = N.off[i] + (int64_t)rows[i].size();
+    N.idx.resize(N.off[n]);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) std::copy(rows[i].begin(), rows[i].end(), N.idx.begin() + N.off[i]);
+}
+
+void neighbours_brute(const OrcParams& P, int64_t n, const double* x, Nbrs& N) {
+    build_rows(n, N, [&](int64_t i, std::vector<int64_t>& row) {
+        double d[3];
         for (int64_t j = 0; j < n; ++j) {
             separation(P, n, x, i, j, d);
-            if (in_support(P, d)) N.idx.push_back(j);
+            if (in_support(P, d)) row.push_back(j);
         }
-        N.off[i + 1] = (int64_t)N.idx.size();
-    }
+    });
 }
 
 /* Cell-list search: bucket the particles by cell, then test the particles of
@@ -244,15 +263,11 @@ bool neighbours_cells(const OrcParams& P, int64_t n, const double* x, Nbrs& N) {
         std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
         for (int64_t i = 0; i < n; ++i) bucket[fill[key[i]]++] = i;
     }
-    N.off.assign(n + 1, 0);
-    N.idx.clear();
     const int s = G.stencil;
-    std::vector<int64_t> row;
-    double d[3];
-    for (int64_t i = 0; i < n; ++i) {
+    build_rows(n, N, [&](int64_t i, std::vector<int64_t>& row) {
+        double d[3];
         int64_t ci[3] = {0, 0, 0};
         for (int k = 0; k < P.dim; ++k) ci[k] = cell_coord(P, G, x[k * n + i], k);
-        row.clear();
         const int oz_lo = P.dim == 3 ? -s : 0, oz_hi = P.dim == 3 ? s : 0;
         for (int oz = oz_lo; oz <= oz_hi; ++oz)
             for (int oy = -s; oy <= s; ++oy)
@@ -278,9 +293,7 @@ bool neighbours_cells(const OrcParams& P, int64_t n, const double* x, Nbrs& N) {
                     }
                 }
         std::sort(row.begin(), row.end());
-        N.idx.insert(N.idx.end(), row.begin(), row.end());
-        N.off[i + 1] = (int64_t)N.idx.size();
-    }
+    });
     return true;
 }
 
@@ -296,8 +309,9 @@ bool neighbours(const OrcParams& P, int64_t n, const double* x, Nbrs& N) {
 
 void density(const OrcParams& P, int64_t n, const double* x, const double* m, const Nbrs& N,
              double* rho) {
-    double d[3];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
+        double d[3];
         double s = 0.0;
         for (int64_t b = N.off[i]; b < N.off[i + 1]; ++b) {
             const int64_t j = N.idx[b];
@@ -335,8 +349,9 @@ double deos(const OrcParams& P, double rho) {
 void momentum(const OrcParams& P, int64_t n, const double* x, const double* v, const double* m,
               const uint8_t* type, const double* rho, const double* p, const Nbrs& N, double* a) {
     const int dim = P.dim;
-    double d[3];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
+        double d[3];
         if (type[i] != 0) {
             for (int k = 0; k < dim; ++k) a[k * n + i] = 0.0;
             continue;
@@ -372,6 +387,7 @@ bool evaluate(const OrcParams& P, int64_t n, const double* x, const double* v, c
     Nbrs& N = keep ? *keep : local;
     if (!neighbours(P, n, x, N)) return false;
     density(P, n, x, m, N, rho);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) p[i] = eos(P, rho[i]);
     momentum(P, n, x, v, m, type, rho, p, N, a);
     return true;
@@ -385,8 +401,9 @@ bool evaluate(const OrcParams& P, int64_t n, const double* x, const double* v, c
 void continuity(const OrcParams& P, int64_t n, const double* x, const double* v, const double* m,
                 const uint8_t* type, const Nbrs& N, double* arho) {
     const int dim = P.dim;
-    double d[3];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
+        double d[3];
         double s = 0.0;
         for (int64_t b = N.off[i]; b < N.off[i + 1]; ++b) {
             const int64_t j = N.idx[b];
@@ -529,6 +546,13 @@ void rhs_adjoint(const OrcParams& P, int64_t n, const double* x, const double* v
 extern "C" {
 
 int orc_version(void) { return 1; }
+
+/* Number of OpenMP threads of the per-destination loops (>= 1); returns the
+ * number in effect. */
+int orc_set_threads(int k) {
+    if (k >= 1) omp_set_num_threads(k);
+    return omp_get_max_threads();
+}
 
 double orc_kernel_w(const OrcParams* P, double r) { return W(*P, r); }
 double orc_kernel_dwdr(const OrcParams* P, double r) { return dWdr(*P, r); }
