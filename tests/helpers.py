@@ -8,10 +8,28 @@ from scipy.spatial import cKDTree
 import sph_workloads as W
 
 
+def support_radius(p: W.Params) -> float:
+    """R = 3h for the quintic spline, 2h for the other kernels."""
+    return (3.0 if p.kernel == W.QUINTIC else 2.0) * p.h
+
+
+# Pairs closer than this to the support radius (relative to R^2) are decided
+# differently by rounding alone: in mixed precision positions are stored as
+# fixed-point offsets of cs / 2^27 from their cell centre (cs <= 2R here), so
+# |r|^2 / R^2 moves by at most about 2 sqrt(3) (cs / R) 2^-27 < 6e-8; in FP64
+# the GPU and the oracle form |r|^2 from the same doubles and differ by at
+# most an ulp or two (fused or separate multiply-adds), which random inputs
+# never meet.
+NEAR_TIE = {0: 0.0, 1: 2e-7}
+
+
 def drop_near_ties(p: W.Params, s: W.State, rel: float) -> W.State:
     """Remove particles with any neighbour at |r^2/R^2 - 1| < rel, so that the
-    neighbour sets do not depend on rounding (a well-posed fixture)."""
-    R = 2 * p.h
+    neighbour sets do not depend on rounding (a well-posed fixture).
+    rel = 0 keeps every particle."""
+    if rel <= 0:
+        return s
+    R = support_radius(p)
     dim = p.dim
     pts = s.x.T.copy()
     box = None
@@ -32,6 +50,33 @@ def drop_near_ties(p: W.Params, s: W.State, rel: float) -> W.State:
     keep[drop] = False
     return W.State(s.x[:, keep].copy(), s.u[:, keep].copy(), s.m[keep].copy(),
                    s.ptype[keep].copy(), np.arange(keep.sum(), dtype=np.int32))
+
+
+def with_near_ties(p: W.Params, s: W.State, count: int, lo: float, hi: float,
+                   seed: int = 0) -> W.State:
+    """Add `count` companion particles, each at |r|^2 = R^2 (1 + e) from a
+    randomly chosen particle, e uniform in [lo, hi] with a random sign and a
+    random direction: pairs inside the +-1e-5 band around the support radius
+    in which the GPU's FP32 filters hand the decision to the exact FP64 test.
+    Companions are fluid particles with the velocity and mass of their
+    partner; ids continue after the last."""
+    rng = np.random.default_rng(seed)
+    R = support_radius(p)
+    dim = p.dim
+    base = rng.choice(s.n, size=count, replace=False)
+    e = rng.uniform(lo, hi, count) * rng.choice([-1.0, 1.0], count)
+    d = rng.normal(size=(dim, count))
+    d /= np.sqrt((d * d).sum(axis=0))
+    x = s.x[:, base] + d * R * np.sqrt(1.0 + e)
+    for k in range(dim):
+        if p.periodic[k]:
+            L = p.hi[k] - p.lo[k]
+            x[k] = p.lo[k] + np.mod(x[k] - p.lo[k], L)
+    n = s.n
+    return W.State(np.concatenate([s.x, x], axis=1), np.concatenate([s.u, s.u[:, base]], axis=1),
+                   np.concatenate([s.m, s.m[base]]),
+                   np.concatenate([s.ptype, np.zeros(count, np.uint8)]),
+                   np.arange(n + count, dtype=np.int32))
 
 
 def shuffled(s: W.State, seed: int = 0) -> W.State:
