@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the WCSPH hot path on one MI355X.
 
-Workload: 2D Taylor-Green vortex, 512 x 512 particles on a lattice jittered by
-+-0.1 dx, periodic unit box, Re = 100, cubic spline h = 1.3 dx, Tait EOS
-c0 = 10 U, predictor-corrector steps with a neighbour rebuild every step.
+Headline workload: the 3D periodic cube of 256^3 = 16,777,216 particles, a
+lattice jittered by +-0.2 dx, velocities N(0, 0.1^2) per component, Wendland
+C2 with h = 1.5 dx (about 113 neighbours per particle), Tait EOS with
+c0 = 10 max|u|, a neighbour rebuild every step.
 
 A step is one full pass of the hot path: half kick + drift + wrap, cell hash,
-counting sort with the stable per-cell rank and state gather, summation
-density + EOS, momentum + closing half kick.  Inputs are resident in device
-memory before the timed region.
+counting sort with the stable per-cell rank and state gather, neighbour
+lists, summation density + EOS, momentum + closing half kick.  Inputs are
+resident in device memory before the timed region.
 
 Prints one JSON line.  value = particle-neighbour interactions per second of
 the mixed-precision step (pair terms in FP32 on cell-relative offsets, FP64
-integration); the full-FP64 step is reported beside it.
+integration); the full-FP64 step is reported beside it, with the normwise
+error of both against the FP64 CPU oracle per field, the 512^2 Taylor-Green
+step, the adjoint/forward time ratio and the oracle's own throughput on a
+bounded sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -185,7 +189,11 @@ def stencil_tests(sph, prm, x) -> int:
 
 
 def roofline(res, wl, prec, steps, tests=None):
-    """Roofline entry of the dominant kernel of the step."""
+    """Roofline entry of the dominant kernel of the step (the one with the
+    largest time per step).  Its algorithmic bytes and flops per launch are
+    priced against both HBM (8 TB/s) and the vector ALU (78.6 TFLOP/s); the
+    bound is the resource with the larger time floor, i.e. ALU when the
+    intensity is at or above the ridge point, and both fractions are kept."""
     kus = res["kernels_us"]
     launches = res["kernels_launches"]
     per_step = {k: kus[k] * launches[k] / steps for k in kus}
@@ -195,37 +203,98 @@ def roofline(res, wl, prec, steps, tests=None):
     tsize = 4 if prec == 1 else 8
     inter_per_launch = res["interactions_timed"] / steps
     nbytes = bytes_per_particle(dom, dim, tsize, wl.params.scheme == 1) * n
+    flops = None
     if dom in PAIR_KERNELS:
         nbytes += 4 * inter_per_launch  # the neighbour lists, written or read once
-    if dom in PAIR_KERNELS:
         if dom == "nlist":
             flops = FLOPS_PER_TEST[dim] * tests
         else:
             # the momentum passes do no arithmetic for the self pair
             pairs = inter_per_launch if dom == "density" else inter_per_launch - n
             flops = FLOPS_PER_PAIR[(dom, dim)] * pairs
-        intensity = flops / nbytes
-        ridge = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-        if intensity >= ridge:
-            ach = flops / avg_s / 1e12
-            out = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS,
-                   "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS}
-        else:
-            ach = nbytes / avg_s / 1e9
-            out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                   "frac": ach / HBM_PEAK_GBS}
+    hbm_ach = nbytes / avg_s / 1e9
+    out = {"kernel": dom, "avg_launch_us": kus[dom], "bytes_per_launch": nbytes,
+           "interactions_per_launch": inter_per_launch,
+           "hbm": {"achieved": hbm_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": hbm_ach / HBM_PEAK_GBS}}
+    ridge = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if flops is not None:
+        alu_ach = flops / avg_s / 1e12
         out["flops_per_launch"] = flops
+        out["intensity_flop_per_byte"] = flops / nbytes
+        out["alu"] = {"achieved": alu_ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": alu_ach / VALU_PEAK_TFLOPS}
+    if flops is not None and flops / nbytes >= ridge:
+        out.update({"bound": "alu", **out["alu"]})
     else:
-        ach = nbytes / avg_s / 1e9
-        out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": ach / HBM_PEAK_GBS}
-    out["kernel"] = dom
-    out["avg_launch_us"] = kus[dom]
-    out["bytes_per_launch"] = nbytes
-    out["interactions_per_launch"] = inter_per_launch
+        out.update({"bound": "hbm", **out["hbm"]})
     if dom == "nlist":
         out["pair_tests_per_launch"] = tests
     out["traffic"] = traffic_from_profile(dom, wl.name)
+    return out
+
+
+def field_errors(sph, torch, wl, prec, nsample=1500):
+    """Normwise error per field (max |f - f_ref| / max |f_ref|, by id) of the
+    GPU against the FP64 oracle.
+    * 3D workloads: rho, p and a of nsample particles after the priming
+      evaluation of the initial state (the oracle evaluates the sample only).
+    * 2D Taylor-Green: one whole step from the GPU's state after 100 steps,
+      both sides starting from the same state: x, u, rho, p, a of every
+      particle."""
+    import numpy as np
+
+    import oracle
+    import sph_workloads as W
+
+    def nw(g, r):
+        g = np.atleast_2d(np.asarray(g, np.float64))
+        r = np.atleast_2d(np.asarray(r, np.float64))
+        return max(float(np.abs(gg - rr).max() / max(np.abs(rr).max(), 1e-300))
+                   for gg, rr in zip(g, r))
+
+    p, s = wl.params, wl.state
+    prm = sph.make_params(p, prec)
+    dp = sph.DeviceParticles.from_state(s, prec, scheme=p.scheme)
+    ws = sph.workspace(prm, s.n)
+    sph.step(prm, dp, 0, ws, prime=True)
+    if p.dim == 3:
+        sph.check(ws)
+        ids = dp.id.cpu().numpy()
+        sub = W.random_subset(s.n, nsample, seed=7)
+        slot = np.empty(s.n, np.int64)
+        slot[ids] = np.arange(s.n)
+        sl = slot[sub]
+        got = {"rho": dp.rho.cpu().numpy()[sl], "p": dp.p.cpu().numpy()[sl],
+               "a": dp.a.cpu().numpy()[:, sl]}
+        del dp, ws
+        torch.cuda.empty_cache()
+        rho, pr, a = oracle.eval_subset(p, s.x, s.u, s.m, s.ptype, sub)
+        ref = {"rho": rho, "p": pr, "a": a}
+        out = {f: nw(got[f], ref[f]) for f in got}
+        out["sample"] = f"{len(sub)} particles after the priming evaluation of the initial state"
+        return out
+    sph.step(prm, dp, 100, ws, prime=False)
+    st = dp.numpy()
+    sph.step(prm, dp, 1, ws, prime=False)
+    sph.check(ws)
+    new = dp.numpy()
+    del dp, ws
+    torch.cuda.empty_cache()
+    ref = oracle.step(p, st["x"], st["u"], st["m"], st["type"], 1,
+                      a=st["a"].astype(np.float64), prime=False)
+    o = np.argsort(new["id"], kind="stable")
+    r = np.argsort(st["id"], kind="stable")
+    out = {}
+    dx = new["x"][:, o] - ref["x"][:, r]
+    for k in range(p.dim):
+        if p.periodic[k]:
+            L = p.hi[k] - p.lo[k]
+            dx[k] -= L * np.round(dx[k] / L)
+    out["x"] = float(np.abs(dx).max() / np.abs(ref["x"]).max())
+    for f in ("u", "rho", "p", "a"):
+        out[f] = nw(new[f][..., o], ref[f][..., r])
+    out["sample"] = "one whole step from the GPU state after 100 steps (every particle)"
     return out
 
 
@@ -258,54 +327,112 @@ def adjoint_ratio(sph, torch, steps=200, k=20, reps=2):
             "forward_ms_per_step": 1e3 * fwd / steps}
 
 
-def cpu_baseline(wl, budget_s=15.0):
-    """The FP64 CPU oracle, single-threaded, on a bounded sample of the same
-    workload: the first steps from the same initial state."""
-    import numpy as np
+def _threads_available() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set."""
+    k = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        k = min(k, int(env))
+    return max(1, k)
 
+
+def _cube_subblock(wl):
+    """The particles of the periodic cube whose lattice sites lie in the
+    corner sub-box [0, L/4)^3, as a periodic box of its own: the same
+    positions, velocities, masses, smoothing length and neighbour counts
+    (jitter never moves a particle across a lattice-cell boundary, so the
+    sub-box tiles periodically like the whole), 1/64 of the particles."""
+    import numpy as np
+    p, s = wl.params, wl.state
+    L = p.hi[0] - p.lo[0]
+    n_side = round(s.n ** (1.0 / 3.0))
+    dx = L / n_side
+    site = np.floor((s.x - np.array(p.lo)[:, None]) / dx).astype(np.int64)
+    keep = np.all(site < n_side // 4, axis=0)
+    sub_hi = tuple(p.lo[k] + (n_side // 4) * dx for k in range(3))
+    ps = p.replace(hi=sub_hi)
+    import sph_workloads as W
+    ss = W.State(s.x[:, keep].copy(), s.u[:, keep].copy(), s.m[keep].copy(),
+                 s.ptype[keep].copy(), np.arange(int(keep.sum()), dtype=np.int32))
+    return ps, ss
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The FP64 CPU oracle on a bounded sample of the same workload, on one
+    thread and on every available host thread (the oracle's OpenMP loops over
+    destination particles; results are bitwise the same).  value is the
+    all-thread rate."""
     import oracle
     p, s = wl.params, wl.state
     if p.scheme == 1:
         return _cpu_baseline_continuity(wl, budget_s)
-    t0 = time.perf_counter()
-    st = oracle.step(p, s.x, s.u, s.m, s.ptype, 0, prime=True)
-    t_prime = time.perf_counter() - t0
-    nsteps = min(wl.steps, max(1, int(budget_s / max(t_prime, 1e-3))))
-    off, _ = oracle.neighbors(p, st["x"])
-    t0 = time.perf_counter()
-    oracle.step(p, st["x"], st["u"], s.m, s.ptype, nsteps, a=st["a"], prime=False)
-    dt = time.perf_counter() - t0
-    inter = float(off[-1]) * nsteps
-    return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
-            "ms_per_step": 1e3 * dt / nsteps,
-            "sample": f"{nsteps} of the {wl.steps} steps of {wl.name} ({s.n} particles) from "
-                      f"the same initial state, FP64 oracle, 1 thread; interactions counted "
-                      f"at the first step's rebuild",
+    if p.dim == 3 and all(p.periodic[:3]) and s.n > 1 << 20:
+        p, s = _cube_subblock(wl)
+        what = (f"the {s.n}-particle corner sub-box [0, L/4)^3 of {wl.name} as a periodic box "
+                f"(same particles, h and neighbour counts)")
+    else:
+        what = f"{wl.name} ({s.n} particles)"
+    off, _ = oracle.neighbors(p, s.x)
+    inter = float(off[-1])
+    del off
+    threads = _threads_available()
+    res = {}
+    for k in sorted({1, threads}):
+        oracle.set_threads(k)
+        t0 = time.perf_counter()
+        st = oracle.step(p, s.x, s.u, s.m, s.ptype, 0, prime=True)
+        t_prime = time.perf_counter() - t0
+        nsteps = min(wl.steps, max(1, int(budget_s / max(t_prime, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.step(p, st["x"], st["u"], s.m, s.ptype, nsteps, a=st["a"], prime=False)
+        dt = time.perf_counter() - t0
+        res[k] = (nsteps, dt)
+    oracle.set_threads(1)
+    nsteps, dt = res[threads]
+    n1, dt1 = res[1]
+    return {"value": inter * nsteps / dt, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle", "ms_per_step": 1e3 * dt / nsteps,
+            "one_thread": {"value": inter * n1 / dt1, "ms_per_step": 1e3 * dt1 / n1,
+                           "steps": n1},
+            "sample": f"{nsteps} predictor-corrector step(s) of {what} from the initial state "
+                      f"after a priming evaluation, FP64 oracle on {threads} thread(s); "
+                      f"interactions counted at the initial rebuild",
             "cpu": _cpu_model()}
 
 
 def _cpu_baseline_continuity(wl, budget_s):
     import oracle
     p, s = wl.params, wl.state
+
     def run(nsteps):
         if p.integrator == 1:  # the example's Euler stage
             oracle.step_continuity(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
         else:
             oracle.step_continuity_pc(p, s.x, s.u, s.rho, s.m, s.ptype, nsteps)
-    t0 = time.perf_counter()
-    run(1)
-    t_one = time.perf_counter() - t0
-    nsteps = min(wl.steps, max(1, int(budget_s / max(t_one, 1e-3))))
     off, _ = oracle.neighbors(p, s.x)
-    t0 = time.perf_counter()
-    run(nsteps)
-    dt = time.perf_counter() - t0
-    inter = float(off[-1]) * nsteps
-    return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
-            "ms_per_step": 1e3 * dt / nsteps,
+    inter = float(off[-1])
+    threads = _threads_available()
+    res = {}
+    for k in sorted({1, threads}):
+        oracle.set_threads(k)
+        t0 = time.perf_counter()
+        run(1)
+        t_one = time.perf_counter() - t0
+        nsteps = min(wl.steps, max(1, int(budget_s / max(t_one, 1e-3))))
+        t0 = time.perf_counter()
+        run(nsteps)
+        res[k] = (nsteps, time.perf_counter() - t0)
+    oracle.set_threads(1)
+    nsteps, dt = res[threads]
+    n1, dt1 = res[1]
+    return {"value": inter * nsteps / dt, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle", "ms_per_step": 1e3 * dt / nsteps,
+            "one_thread": {"value": inter * n1 / dt1, "ms_per_step": 1e3 * dt1 / n1,
+                           "steps": n1},
             "sample": f"{nsteps} of the {wl.steps} steps of {wl.name} ({s.n} particles) from "
-                      f"the initial state, FP64 oracle, 1 thread; interactions counted at "
-                      f"the first step's rebuild",
+                      f"the initial state, FP64 oracle on {threads} thread(s); interactions "
+                      f"counted at the first step's rebuild",
             "cpu": _cpu_model()}
 
 
@@ -319,12 +446,24 @@ def _cpu_model():
     return "unknown"
 
 
+METRIC = ("particle-neighbour interactions/s + ms/step (FP32 vs FP64); "
+          "adjoint/forward ratio")
+
+
+def summary(res):
+    """The timing keys of one precision's run (without the per-kernel detail)."""
+    if res is None:
+        return None
+    return {k: res[k] for k in ("ms_per_step", "interactions_per_s", "interactions")
+            if k in res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tg512")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube256")
     ap.add_argument("--cell-div", type=int, default=0,
                     help="cells per support radius (default: the workload's)")
     ap.add_argument("--nbr-cap", type=int, default=0,
@@ -333,6 +472,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the per-field errors against the oracle")
+    ap.add_argument("--no-tg512", action="store_true",
+                    help="skip the 512^2 Taylor-Green step reported beside the headline")
+    ap.add_argument("--tg512-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (8 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run")
@@ -358,30 +502,55 @@ def main():
     import paper_1909_04504_amd as sph
     import sph_workloads as W
 
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     wl = W.workload(args.workload)
     if args.cell_div:
         wl.params = wl.params.replace(cell_div=args.cell_div)
-    print(f"# workload {wl.name}: {wl.description}; n={wl.state.n}", file=sys.stderr, flush=True)
+    note(f"# workload {wl.name}: {wl.description}; n={wl.state.n}")
     mixed = run_precision(sph, torch, wl, sph.FP32_MIXED, args.steps, args.warmup, True,
                           args.nbr_cap)
-    print(f"# fp32-mixed: {mixed['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+    note(f"# fp32-mixed: {mixed['ms_per_step']:.4f} ms/step")
     fp64 = None
     if not args.no_fp64:
         fp64 = run_precision(sph, torch, wl, sph.FP64, args.steps, args.warmup, True,
                              args.nbr_cap)
-        print(f"# fp64: {fp64['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+        note(f"# fp64: {fp64['ms_per_step']:.4f} ms/step")
     rl = roofline(mixed, wl, sph.FP32_MIXED, args.steps, mixed["pair_tests"])
+    errors = None
+    if not args.no_errors and wl.params.scheme == 0:
+        errors = {"fp32_mixed": field_errors(sph, torch, wl, sph.FP32_MIXED)}
+        if not args.no_fp64:
+            errors["fp64"] = field_errors(sph, torch, wl, sph.FP64)
+        note(f"# field errors vs oracle: {json.dumps(errors)}")
+    tg = None
+    if not args.no_tg512 and wl.name != "tg512":
+        wl2 = W.workload("tg512")
+        tg = {"workload": wl2.name, "description": wl2.description, "particles": wl2.state.n,
+              "steps": args.tg512_steps,
+              "fp32_mixed": summary(run_precision(sph, torch, wl2, sph.FP32_MIXED,
+                                                  args.tg512_steps, 10, False))}
+        if not args.no_fp64:
+            tg["fp64"] = summary(run_precision(sph, torch, wl2, sph.FP64, args.tg512_steps,
+                                               10, False))
+        if not args.no_errors:
+            tg["errors"] = {"fp32_mixed": field_errors(sph, torch, wl2, sph.FP32_MIXED)}
+            if not args.no_fp64:
+                tg["errors"]["fp64"] = field_errors(sph, torch, wl2, sph.FP64)
+        note(f"# tg512: {tg['fp32_mixed']['ms_per_step']:.4f} ms/step mixed")
+        del wl2
     adj = None
     if not args.no_adjoint:
         adj = adjoint_ratio(sph, torch)
-        print(f"# adjoint/forward: {adj['ratio']:.2f}", file=sys.stderr, flush=True)
+        note(f"# adjoint/forward: {adj['ratio']:.2f}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl)
-        print(f"# cpu oracle: {cpu['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+        note(f"# cpu oracle: {cpu['ms_per_step']:.1f} ms/step on {cpu['cores']} thread(s)")
 
     out = {
-        "metric": "particle-neighbour interactions/s (mixed precision step)",
+        "metric": METRIC,
         "value": mixed["interactions_per_s"],
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -402,7 +571,11 @@ def main():
         "roofline_detail": rl,
         "fp32_mixed": mixed,
         "fp64": fp64,
+        "fp64_ms_per_step": fp64["ms_per_step"] if fp64 else None,
+        "fp64_interactions_per_s": fp64["interactions_per_s"] if fp64 else None,
         "fp64_vs_mixed_time": (fp64["ms_per_step"] / mixed["ms_per_step"]) if fp64 else None,
+        "errors_vs_oracle": errors,
+        "tg512": tg,
         "adjoint_forward_ratio": adj["ratio"] if adj else None,
         "adjoint": adj,
         "cpu_baseline": cpu,

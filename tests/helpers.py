@@ -58,20 +58,36 @@ def with_near_ties(p: W.Params, s: W.State, count: int, lo: float, hi: float,
     randomly chosen particle, e uniform in [lo, hi] with a random sign and a
     random direction: pairs inside the +-1e-5 band around the support radius
     in which the GPU's FP32 filters hand the decision to the exact FP64 test.
-    Companions are fluid particles with the velocity and mass of their
-    partner; ids continue after the last."""
+    On periodic axes companions are wrapped into the box; on the others only
+    draws that land inside [lo, hi) are kept, so the fixture never trips the
+    library's out-of-domain flag.  Companions are fluid particles with the
+    velocity and mass of their partner; ids continue after the last."""
     rng = np.random.default_rng(seed)
     R = support_radius(p)
     dim = p.dim
-    base = rng.choice(s.n, size=count, replace=False)
-    e = rng.uniform(lo, hi, count) * rng.choice([-1.0, 1.0], count)
-    d = rng.normal(size=(dim, count))
-    d /= np.sqrt((d * d).sum(axis=0))
-    x = s.x[:, base] + d * R * np.sqrt(1.0 + e)
-    for k in range(dim):
-        if p.periodic[k]:
+    xs, bases = [], []
+    have = 0
+    for _ in range(64):
+        base = rng.choice(s.n, size=count, replace=count > s.n)
+        e = rng.uniform(lo, hi, count) * rng.choice([-1.0, 1.0], count)
+        d = rng.normal(size=(dim, count))
+        d /= np.sqrt((d * d).sum(axis=0))
+        x = s.x[:, base] + d * R * np.sqrt(1.0 + e)
+        inside = np.ones(count, bool)
+        for k in range(dim):
             L = p.hi[k] - p.lo[k]
-            x[k] = p.lo[k] + np.mod(x[k] - p.lo[k], L)
+            if p.periodic[k]:
+                x[k] = p.lo[k] + np.mod(x[k] - p.lo[k], L)
+            else:
+                inside &= (x[k] >= p.lo[k]) & (x[k] < p.hi[k])
+        xs.append(x[:, inside])
+        bases.append(base[inside])
+        have += int(inside.sum())
+        if have >= count:
+            break
+    x = np.concatenate(xs, axis=1)[:, :count]
+    base = np.concatenate(bases)[:count]
+    assert x.shape[1] == count, "could not place the companions inside the box"
     n = s.n
     return W.State(np.concatenate([s.x, x], axis=1), np.concatenate([s.u, s.u[:, base]], axis=1),
                    np.concatenate([s.m, s.m[base]]),

@@ -20,3 +20,13 @@ def test_near_tie_fixture_has_band_pairs():
     r2 = (d * d).sum(axis=0) / R2
     band = (np.abs(r2 - 1) < 1e-5) & (np.abs(r2 - 1) >= 5e-7 * 0.99)
     assert band.sum() >= 400
+
+
+def test_near_tie_fixture_stays_inside_walled_box():
+    """On non-periodic axes the companions land inside [lo, hi), so a walled
+    fixture never sets the library's out-of-domain flag."""
+    for case in ("box2d", "sparse2d"):
+        p, s = make_case(case)
+        s = with_near_ties(p, s, min(400, s.n // 4), 1e-12, 1e-5, seed=21)
+        for k in range(p.dim):
+            assert np.all(s.x[k] >= p.lo[k]) and np.all(s.x[k] < p.hi[k]), (case, k)
