@@ -110,6 +110,14 @@ typedef struct {
     int32_t scheme;       /* sph_scheme */
     int32_t integrator;   /* sph_integrator (sph_step only); EULER needs the
                            * continuity scheme */
+    int32_t pair_tiles;   /* 3D mixed-precision summation passes (Section
+                           * 2.2's cell grid cut into boxes whose particles
+                           * and neighbour cells are staged in on-chip
+                           * memory): 0 = used where they apply (default),
+                           * < 0 = never (lists read from global memory),
+                           * k > 0 = used with at most k staged particles per
+                           * box (larger boxes take the cell walk).  Results do
+                           * not depend on it. */
 } sph_params;
 
 /* Particle arrays (device pointers, caller-owned). */

@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
                 ("periodic", _i32 * 3), ("nbr_cap", _i32),
                 ("h", _d), ("rho0", _d), ("c0", _d), ("nu", _d), ("eta", _d), ("dt", _d),
                 ("g", _d * 3), ("lo", _d * 3), ("hi", _d * 3),
-                ("scheme", _i32), ("integrator", _i32)]
+                ("scheme", _i32), ("integrator", _i32), ("pair_tiles", _i32)]
 
 
 class Particles(ctypes.Structure):
@@ -90,15 +90,18 @@ def _rc(code: int):
         raise SphError(code, lib().sph_last_error().decode())
 
 
-def make_params(p, precision: int = FP64, nbr_cap: int = 0) -> Params:
+def make_params(p, precision: int = FP64, nbr_cap: int = 0, pair_tiles: int = 0) -> Params:
     """C parameter struct from a sph_workloads.Params-like object.  nbr_cap:
-    neighbour-list capacity per particle (0 default, < 0 cell walks only)."""
+    neighbour-list capacity per particle (0 default, < 0 cell walks only);
+    pair_tiles: LDS-staged tiles of the 3D mixed-precision passes (0 where
+    they apply, < 0 never, k > 0 at most k staged particles per tile)."""
     c = Params()
     c.dim, c.kernel, c.precision, c.cell_div = p.dim, p.kernel, precision, p.cell_div
     for k in range(3):
         c.periodic[k] = int(p.periodic[k])
         c.g[k], c.lo[k], c.hi[k] = float(p.g[k]), float(p.lo[k]), float(p.hi[k])
     c.nbr_cap = int(nbr_cap)
+    c.pair_tiles = int(pair_tiles)
     c.scheme = int(getattr(p, "scheme", 0))
     c.integrator = int(getattr(p, "integrator", 0))
     c.h, c.rho0, c.c0, c.nu, c.eta, c.dt = p.h, p.rho0, p.c0, p.nu, p.eta, p.dt

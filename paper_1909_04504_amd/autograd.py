@@ -22,13 +22,14 @@ class SPHRollout(torch.autograd.Function):
     Inputs: u0 (dim, n) float64 CUDA tensor in particle-id order, nu a 0-d
     float64 tensor; params (sph_workloads.Params-like), x0, m, ptype as device
     tensors or arrays; nsteps; k (checkpoint interval); precision; nbr_cap
-    (neighbour-list capacity, as in make_params).
+    and pair_tiles (as in make_params).
     """
 
     @staticmethod
-    def forward(ctx, u0, nu, params, x0, m, ptype, nsteps, k, precision=FP64, nbr_cap=0):
+    def forward(ctx, u0, nu, params, x0, m, ptype, nsteps, k, precision=FP64, nbr_cap=0,
+                pair_tiles=0):
         p = params.replace(nu=float(nu.item()))
-        prm = make_params(p, precision, nbr_cap)
+        prm = make_params(p, precision, nbr_cap, pair_tiles)
         n = u0.shape[1]
         dim = u0.shape[0]
         pid = torch.arange(n, dtype=torch.int32, device=u0.device)
@@ -68,8 +69,10 @@ class SPHRollout(torch.autograd.Function):
         grad_u0 = torch.zeros((dim, n), dtype=torch.float64, device=dev)
         grad_u0[:, c0.id.long()] = lam[dim:2 * dim]
         ctx.state = None
-        return grad_u0, dJ[0], None, None, None, None, None, None, None, None
+        return grad_u0, dJ[0], None, None, None, None, None, None, None, None, None
 
 
-def rollout_ke(u0, nu, params, x0, m, ptype, nsteps, k, precision=FP64, nbr_cap=0):
-    return SPHRollout.apply(u0, nu, params, x0, m, ptype, nsteps, k, precision, nbr_cap)
+def rollout_ke(u0, nu, params, x0, m, ptype, nsteps, k, precision=FP64, nbr_cap=0,
+               pair_tiles=0):
+    return SPHRollout.apply(u0, nu, params, x0, m, ptype, nsteps, k, precision, nbr_cap,
+                            pair_tiles)

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 SRC = os.path.join(CSRC, "sph.hip")
 PART = os.path.join(CSRC, "sph_part.hip")
 DEPS = [SRC, PART] + [os.path.join(CSRC, f) for f in
-                      ("sph_engine.hpp", "sph_kernels.hpp", "sph_adjoint.hpp")] + \
+                      ("sph_engine.hpp", "sph_kernels.hpp", "sph_adjoint.hpp", "sph_tiles.hpp")] + \
        [os.path.join(ROOT, "include", "sph.h")]
 LIB = os.path.join(HERE, "libsph_mi355x.so")
 OBJDIR = os.path.join(HERE, "_build")

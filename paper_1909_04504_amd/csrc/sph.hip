@@ -40,7 +40,7 @@ size_t sph_workspace_bytes(const sph_params* prm, int64_t n, int64_t adjoint_k) 
     sph::Grid G;
     int64_t ncells;
     if (make_grid(prm, &G, &ncells) != SPH_OK) return 0;
-    return make_layout(prm, n, ncells, adjoint_k).bytes;
+    return make_layout(prm, G, n, ncells, adjoint_k).bytes;
 }
 
 int sph_bin_sort(const sph_params* prm, sph_particles* pa, void* ws, size_t ws_bytes,

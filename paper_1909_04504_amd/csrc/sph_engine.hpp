@@ -7,6 +7,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,6 +19,7 @@
 #include "sph.h"
 #include "sph_kernels.hpp"
 #include "sph_adjoint.hpp"
+#include "sph_tiles.hpp"
 
 namespace sph_host {
 
@@ -60,12 +62,14 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + sph::kBlock - 1) 
 enum KernelId {
     K_FILL, K_HASH, K_CHUNK_SUM, K_CHUNK_SCAN, K_SCATTER, K_RANK_GATHER, K_PACK, K_DENSITY,
     K_MOMENTUM, K_EOS, K_NBR_COUNT, K_NBR_FILL, K_CELL_RANGES, K_COPY, K_DIAG, K_ADJ_SEED,
-    K_ADJ_PAIR1, K_ADJ_PAIR2, K_ADJ_REDUCE, K_ADJ_KICK, K_NLIST, K_CONT, K_COUNT
+    K_ADJ_PAIR1, K_ADJ_PAIR2, K_ADJ_REDUCE, K_ADJ_KICK, K_NLIST, K_CONT, K_TILE_BUILD,
+    K_TILE_DENSITY, K_TILE_MOMENTUM, K_TILE_FALLBACK, K_COUNT
 };
 inline const char* const kKernelNames[K_COUNT] = {
     "fill", "drift_hash", "chunk_sum", "chunk_scan", "scatter", "rank_gather", "pack",
     "density", "momentum", "eos", "nbr_count", "nbr_fill", "cell_ranges", "copy_state", "diag",
-    "adj_seed", "adj_pair1", "adj_pair2", "adj_reduce", "adj_kick", "nlist", "cont_momentum"};
+    "adj_seed", "adj_pair1", "adj_pair2", "adj_reduce", "adj_kick", "nlist", "cont_momentum",
+    "tile_build", "tile_density", "tile_momentum", "tile_fallback"};
 
 struct Timer {
     bool on = false;
@@ -107,18 +111,23 @@ inline Timer g_timer;
 // dispatch itself (hipExtLaunchKernel), so the elapsed time is the kernel's
 // own duration.
 template <typename... KArgs, typename... Args>
-void launch(int id, void (*k)(KArgs...), unsigned grid, hipStream_t st, Args... args) {
+void launch_b(int id, void (*k)(KArgs...), unsigned grid, unsigned block, hipStream_t st,
+              Args... args) {
     if (g_timer.on) {
         hipEvent_t a = g_timer.get(), b = g_timer.get();
         if (a && b) {
-            hipExtLaunchKernelGGL(k, dim3(grid), dim3(sph::kBlock), 0, st, a, b, 0,
+            hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), 0, st, a, b, 0,
                                   static_cast<KArgs>(args)...);
             g_timer.pending.push_back({id, a, b});
             if (g_timer.pending.size() > 200000) g_timer.fold();
             return;
         }
     }
-    hipLaunchKernelGGL(k, dim3(grid), dim3(sph::kBlock), 0, st, static_cast<KArgs>(args)...);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), 0, st, static_cast<KArgs>(args)...);
+}
+template <typename... KArgs, typename... Args>
+void launch(int id, void (*k)(KArgs...), unsigned grid, hipStream_t st, Args... args) {
+    launch_b(id, k, grid, sph::kBlock, st, args...);
 }
 
 // ---------------------------------------------------------------------------
@@ -223,6 +232,61 @@ inline uint32_t list_cap(const sph_params* p, int64_t n) {
     return p->dim == 2 ? 64u : 192u;
 }
 
+// Tiles of the 3D mixed-precision summation passes (ntiles = 0: not used).
+// Boxes of 8 x 4 x 4 cells with half-size cells (a union of 12 x 8 x 8
+// cells, about 2,600 particles on the 256^3 lattice at h = 1.5 dx), and of
+// 4 x 4 x 2 or 2 x 2 x 2 whole cells (by the mean occupancy).
+inline sph::Tiles make_tiles(const sph_params* p, const sph::Grid& G, int64_t n, int64_t ncells) {
+    sph::Tiles T;
+    std::memset(&T, 0, sizeof T);
+    if (p->dim != 3 || p->precision != SPH_FP32_MIXED || p->scheme != SPH_SCHEME_SUMMATION ||
+        p->pair_tiles < 0 || list_cap(p, n) < 8)
+        return T;
+    T.S = G.S;
+    if (T.S == 2) {
+        T.tw = 8; T.th = 4; T.td = 4;
+    } else if ((double)n / (double)ncells <= 19.0) {
+        T.tw = 4; T.th = 4; T.td = 2;
+    } else {
+        T.tw = 2; T.th = 2; T.td = 2;
+    }
+    T.uw = T.tw + 2 * T.S;
+    T.uh = T.th + 2 * T.S;
+    T.ud = T.td + 2 * T.S;
+    int64_t nt = 1;
+    for (int k = 0; k < 3; ++k) {
+        const int t = k == 0 ? T.tw : (k == 1 ? T.th : T.td);
+        T.nt[k] = (G.nc[k] + t - 1) / t;
+        nt *= T.nt[k];
+        T.csf[k] = (float)G.cs[k];
+        T.inv_csf[k] = (float)(1.0 / G.cs[k]);
+    }
+    T.cen[0] = T.uw / 2;
+    T.cen[1] = T.uh / 2;
+    T.cen[2] = T.ud / 2;
+    const double R = support_radius(p);
+    T.rclip2 = (float)(R * R * (1.0 + 1e-4));
+    T.clip_pad = (float)(1e-4 * std::min(G.cs[0], std::min(G.cs[1], G.cs[2])));
+    T.cap = p->pair_tiles > 0 ? std::min(p->pair_tiles, sph::kTileCap) : sph::kTileCap;
+    if (nt > (int64_t)1 << 30 || T.uw > sph::kTileUnionAxisMax || T.uh > sph::kTileUnionAxisMax ||
+        T.ud > sph::kTileUnionAxisMax || T.uw * T.uh * T.ud > sph::kTileCellsMax ||
+        T.th * T.td > sph::kTileRowsMax) {
+        std::memset(&T, 0, sizeof T);
+        return T;
+    }
+    T.ntiles = (int)nt;
+    return T;
+}
+inline unsigned fallback_blocks(int64_t n) {
+    return std::min<unsigned>((unsigned)sph::kFallbackBlocks, blocks_for(n));
+}
+inline uint32_t next_tile_epoch() {
+    static std::atomic<uint32_t> e{0};
+    uint32_t v = ++e;
+    if (v == 0) v = ++e;
+    return v;
+}
+
 inline int check_particles(const sph_params* p, const sph_particles* pa) {
     if (!pa) return fail(SPH_EINVAL, "particles is NULL");
     if (pa->n < 1 || pa->n >= ((int64_t)1 << 31) - sph::kScanChunk)
@@ -253,6 +317,7 @@ struct SlotOff {
 struct Layout {
     size_t flags, counts, start, chunks, key, tmp, perm, skey, ncnt, lcnt, list;
     uint32_t cap;
+    sph::Tiles tiles;
     StateOff s1, s2;
     size_t pos, vel, rp, diag;
     // adjoint (present when adj_k > 0; the tape is the last region)
@@ -295,9 +360,12 @@ inline NlistShape nlist_shape(int64_t n, int64_t ncells) {
     return {(unsigned)((waves + per_block - 1) / per_block), kNlistSlots, 1};
 }
 
-inline Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_t adj_k) {
+inline Layout make_layout(const sph_params* p, const sph::Grid& G, int64_t n, int64_t ncells,
+                          int64_t adj_k) {
     Layout L;
     std::memset(&L, 0, sizeof L);
+    L.tiles = make_tiles(p, G, n, ncells);
+    const size_t ntiles = (size_t)L.tiles.ntiles;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -327,7 +395,9 @@ inline Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_
     // header (flag word at 0, number of interaction counters at 8), then one
     // 64-bit interaction counter per block of the counting kernel (k_nlist,
     // or k_density without lists) from offset 16
-    L.flags = take(16 + 8 * (size_t)std::max(nlist_shape(n, ncells).blocks, blocks_for(n)));
+    // (and the tile passes' fallback epoch at offset 4)
+    L.flags = take(16 + 8 * std::max<size_t>(std::max(nlist_shape(n, ncells).blocks, blocks_for(n)),
+                                             ntiles));
     L.counts = take(4 * (size_t)ncells);
     L.start = take(4 * ((size_t)ncells + 1));
     L.chunks = take(8 * nchunks);
@@ -344,7 +414,8 @@ inline Layout make_layout(const sph_params* p, int64_t n, int64_t ncells, int64_
     L.pos = take(4 * T * N);
     L.vel = take(4 * T * N);
     L.rp = take(2 * T * N);
-    L.diag = take(8 * 4 * (size_t)blocks_for(n));
+    // diagnostics partials: per block, or per tile and fallback block
+    L.diag = take(8 * 4 * std::max<size_t>(blocks_for(n), ntiles + fallback_blocks(n)));
     L.adj_k = adj_k;
     if (adj_k > 0) {
         L.s2 = take_state();
@@ -613,9 +684,81 @@ struct Engine {
     }
     const uint32_t* list_or_null() const { return L.cap ? list() : nullptr; }
 
+    // --- LDS-tiled passes (3D mixed precision, summation scheme) -----------
+    static constexpr bool kTileable = DIM == 3 && std::is_same<T, float>::value;
+    bool tiled() const { return kTileable && L.tiles.ntiles > 0; }
+    uint32_t tcap() const { return L.cap & ~7u; }
+    uint32_t* fbword() const { return (uint32_t*)(ws + L.flags + 4); }
+    uint32_t tile_epoch = 0;
+
+    // Tile lists of the current records and, with_density, the density (and
+    // EOS) over them; then the fallback density of the targets the tiles left.
+    int tile_lists(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_density,
+                   bool with_eos, bool count_pairs) {
+        if constexpr (kTileable) {
+            tile_epoch = next_tile_epoch();
+            const sph::Tiles TL = L.tiles;
+            with_reach([&](auto R) {
+                launch_b(K_TILE_BUILD, sph::k_tile_build<decltype(R)::value>, (unsigned)TL.ntiles,
+                         sph::kTileThreads, st, n, G, C, TL, TL.cap, pos(), cs, ce, tcap(),
+                         (uint4*)list(), lcnt(), count_pairs ? 1 : 0, pairs(), tile_epoch,
+                         fbword());
+            });
+            SPH_TRY(launch_check("k_tile_build"));
+            if (!with_density) return SPH_OK;
+            with_reach([&](auto R) {
+                launch_b(K_TILE_DENSITY, sph::k_tile_density<decltype(R)::value, KERNEL>,
+                         (unsigned)TL.ntiles, sph::kTileThreads, st, n, G, C, TL, TL.cap, pos(), cs,
+                         ce, tcap(), (const uint4*)list(), lcnt(), (float*)s.rho, (float*)s.p,
+                         vel(), rp(), with_eos ? 1 : 0);
+            });
+            SPH_TRY(launch_check("k_tile_density"));
+            with_reach([&](auto R) {
+                launch(K_TILE_FALLBACK, sph::k_tile_fallback_density<decltype(R)::value, KERNEL>,
+                       fallback_blocks(n), st, n, G, C, skey(), pos(), cs, ce, lcnt(), tcap(),
+                       (float*)s.rho, (float*)s.p, vel(), rp(), with_eos ? 1 : 0,
+                       count_pairs ? 1 : 0, pairs(), tile_epoch, fbword());
+            });
+            return launch_check("k_tile_fallback_density");
+        }
+        return fail(SPH_EINVAL, "tiled passes need 3D mixed precision");
+    }
+
+    // Tiled momentum of the targets with complete tile lists, then the
+    // fallback momentum; diagnostics over both kernels' partial sums.
+    int tile_momentum(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool kick,
+                      bool drift, double* diag_out) {
+        if constexpr (kTileable) {
+            const sph::Tiles TL = L.tiles;
+            const unsigned fb = fallback_blocks(n);
+            const int stride = TL.ntiles + (int)fb;
+            double* part = diag_out ? (double*)(ws + L.diag) : nullptr;
+            with_reach([&](auto R) {
+                launch_b(K_TILE_MOMENTUM, sph::k_tile_momentum<decltype(R)::value, KERNEL>,
+                         (unsigned)TL.ntiles, sph::kTileThreads, st, n, G, C, TL, TL.cap, pos(),
+                         vel(), rp(), s.type, cs, ce, tcap(), (const uint4*)list(), lcnt(), s,
+                         kick ? 1 : 0, drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(),
+                         flags(), part, stride);
+            });
+            SPH_TRY(launch_check("k_tile_momentum"));
+            with_reach([&](auto R) {
+                launch(K_TILE_FALLBACK, sph::k_tile_fallback_momentum<decltype(R)::value, KERNEL>,
+                       fb, st, n, G, C, skey(), pos(), vel(), rp(), s.type, cs, ce, lcnt(), tcap(),
+                       s, kick ? 1 : 0, drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(),
+                       flags(), part ? part + TL.ntiles : nullptr, stride, tile_epoch, fbword());
+            });
+            SPH_TRY(launch_check("k_tile_fallback_momentum"));
+            if (!diag_out) return SPH_OK;
+            launch(K_DIAG, sph::k_diag_final<DIM>, 1, st, stride, part, diag_out);
+            return launch_check("k_diag_final");
+        }
+        return fail(SPH_EINVAL, "tiled passes need 3D mixed precision");
+    }
+
     // Lists of the current records, then the density over them; without
     // lists the density walk counts the interactions.
     int density(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool with_eos) {
+        if (tiled()) return tile_lists(s, cs, ce, true, with_eos, true);
         if (L.cap) SPH_TRY(nlist(cs, ce, true));
         with_reach([&](auto R) {
             launch(K_DENSITY, sph::k_density<DIM, decltype(R)::value, KERNEL, T>, blocks_for(n), st,
@@ -629,6 +772,7 @@ struct Engine {
     // diag_out: KE and momentum after the kick, 1 + DIM doubles.
     int momentum(const sph::State& s, const uint32_t* cs, const uint32_t* ce, bool kick,
                  bool drift = false, double* diag_out = nullptr) {
+        if (tiled()) return tile_momentum(s, cs, ce, kick, drift, diag_out);
         double* part = diag_out ? (double*)(ws + L.diag) : nullptr;
         const unsigned nb = blocks_for(n);
         {
@@ -677,7 +821,10 @@ struct Engine {
     int momentum_only(sph_particles* pa, const uint32_t* cs, const uint32_t* ce) {
         const sph::State user = user_state(pa, prm);
         SPH_TRY(pack(user, true));
-        if (L.cap) SPH_TRY(nlist(cs, ce, false));
+        if (tiled())
+            SPH_TRY(tile_lists(user, cs, ce, false, false, false));
+        else if (L.cap)
+            SPH_TRY(nlist(cs, ce, false));
         return momentum(user, cs, ce, false);
     }
 
@@ -878,7 +1025,9 @@ struct Engine {
         SPH_TRY(zero_counts());
         SPH_TRY(sort_into(user, s1, false, false));
         SPH_TRY(density(s1, start(), start() + 1, true));
-        SPH_TRY(adjoint_rhs(nullptr, lam_a, n, 0.0, s1.type, perm(), dJ, false));
+        // the adjoint passes read global-format lists: rebuilt if the density
+        // went through the tiles
+        SPH_TRY(adjoint_rhs(nullptr, lam_a, n, 0.0, s1.type, perm(), dJ, tiled()));
         launch(K_ADJ_KICK, sph::k_adj_accum<DIM>, blocks_for(n), st,
             n, (const double*)(ws + L.lxd), (const double*)(ws + L.lvd), s1.type, perm(), lam_x,
             lam_u);
@@ -896,7 +1045,7 @@ int make_engine(const sph_params* p, const sph_particles* pa, void* ws, size_t w
     E->prm = p;
     E->ncells = ncells;
     E->n = (int)pa->n;
-    E->L = make_layout(p, pa->n, ncells, adj_k);
+    E->L = make_layout(p, E->G, pa->n, ncells, adj_k);
     if (!ws) return fail(SPH_EINVAL, "workspace is NULL");
     if ((uintptr_t)ws % 256 != 0) return fail(SPH_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < E->L.bytes)

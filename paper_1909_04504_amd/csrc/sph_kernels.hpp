@@ -1118,6 +1118,33 @@ __device__ __forceinline__ double4 rec_bcast(const double4& r, int t) {
     return o;
 }
 
+// Adds a block's interaction count to its own counter pairs[blk] (plain
+// read-modify-write: each block owns its slot and launches are stream
+// ordered); block 0 raises pairs[-1], the number of counters the reader sums,
+// to at least the grid size.
+__device__ __forceinline__ void add_pairs(unsigned long long* __restrict__ pairs, int blk,
+                                          unsigned long long t) {
+    pairs[blk] += t;
+    if (blk == 0 && pairs[-1] < (unsigned long long)gridDim.x)
+        pairs[-1] = (unsigned long long)gridDim.x;
+}
+
+// Block-wide sum of a per-thread count into the block's counter (kBlock
+// threads).
+__device__ __forceinline__ void block_count(uint32_t cnt, unsigned long long* __restrict__ pairs,
+                                            int blk) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    __shared__ uint32_t wcnt[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
+        add_pairs(pairs, blk, t);
+    }
+}
+
 // Coordinates of the list builder's filter test, in FP32, relative to the
 // centre of the target cell c: the target's position, and the position of
 // candidate j's image for stencil offset o / periodic image w.  Their
@@ -1377,18 +1404,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
             }
         }
     }
-    if (!count_pairs) return;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) total += __shfl_xor(total, d, 64);
-    __shared__ uint32_t wcnt[kBlock / 64];
-    if (lane == 0) wcnt[threadIdx.x >> 6] = total;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
-        pairs[blk] += t;
-        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
-    }
+    if (count_pairs) block_count(total, pairs, blk);
 }
 
 // Neighbour lists of all particles (Sec. 2.2), one particle per lane: the
@@ -1421,25 +1437,72 @@ __global__ __launch_bounds__(kBlock) void k_nlist_walk(int n, Grid G, PairConst<
                                });
         ncnt[i] = cnt;
     }
-    if (!count_pairs) return;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
-    __shared__ uint32_t wcnt[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
-        pairs[blk] += t;
-        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
-    }
+    if (count_pairs) block_count(cnt, pairs, blk);
 }
 
-// Summation density (eq. 2) and, if with_eos, the Tait EOS (eq. eos) with
-// P = p / rho^2 packed for the momentum pass, over the neighbour lists (or
-// the cell walk).  Without lists (list == nullptr) and with count_pairs, the
-// number of interactions |N(i)| is added to the block's own counter
-// pairs[block] as the list build does otherwise.
+// Pair terms shared by the list, walk and tile passes (one definition, so the
+// paths round alike; multiply-adds are fused within each statement only).
+//
+// Summation density (eq. 2), FP64 in both precisions: acc += m_j W(|r_ij|).
+template <int KERNEL, typename T>
+__device__ __forceinline__ void density_add(double& acc, const Geom<T>& g, double mj,
+                                            const PairConst<T>& C) {
+    const double q = density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
+    acc += mj * kernel_w<KERNEL, double>(q, C.sigma_d);
+}
+
+// Momentum terms of pair (i, j) (eqs. mom:sph:press, mom:sph:visc):
+//   a_i += m_j [ -(P_i + P_j) F r_ij + 4 nu/(rho_i+rho_j) F |r|^2/(|r|^2 + eta h^2) v_ij ]
+// with F = (dW/dr)/r.  The self pair (j = i) is not skipped: r = 0 and
+// v_i - v_i = 0 multiply finite factors (F is finite at r = 0 and the viscous
+// factor is taken as 0 there), so it adds exactly zero, without a branch.
+template <int DIM, int KERNEL, typename T>
+__device__ __forceinline__ void momentum_add(T& ax, T& ay, T& az, const Geom<T>& g, T mj,
+                                             const typename Vec4<T>::type& vi,
+                                             const typename Vec2<T>::type& rpi,
+                                             const typename Vec4<T>::type& vj,
+                                             const typename Vec2<T>::type& rpj,
+                                             const PairConst<T>& C) {
+    const T r2 = g.r2;
+    const T F = kernel_f_r2<KERNEL, T>(r2, C);
+    const T pres = -(rpi.y + rpj.y) * F;
+    const T visc = r2 > T(0) ? C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2))
+                             : T(0);
+    ax += mj * (pres * g.d[0] + visc * (vi.x - vj.x));
+    ay += mj * (pres * g.d[1] + visc * (vi.y - vj.y));
+    if (DIM == 3) az += mj * (pres * g.d[2] + visc * (vi.z - vj.z));
+}
+
+// Summation density (eq. 2) of sorted slot i and, if with_eos, the Tait EOS
+// (eq. eos) with P = p / rho^2 packed for the momentum pass, over its
+// neighbour list (or the cell walk).  Returns |N(i)|.
+template <int DIM, int SR, int KERNEL, typename T>
+__device__ __forceinline__ uint32_t density_one(
+    int i, const Grid& G, const PairConst<T>& C, const uint32_t* __restrict__ skey,
+    const typename Rec<T>::type* __restrict__ pos, const uint32_t* __restrict__ cstart,
+    const uint32_t* __restrict__ cend, int n, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ ncnt, uint32_t cap, void* __restrict__ rho_out, int rho64,
+    T* __restrict__ p_out, typename Vec4<T>::type* __restrict__ vel,
+    typename Vec2<T>::type* __restrict__ rp, int with_eos) {
+    const typename Rec<T>::type ri = pos[i];
+    // The density terms are FP64 in both precisions: the EOS multiplies
+    // density rounding by ~7 B / rho0 before it reaches the forces.
+    double acc = 0.0;
+    uint32_t cnt = 0;
+    for_each_neighbor<DIM, SR, T>(i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt,
+                                  cap,
+                                  [&](uint32_t, const typename Rec<T>::type& rj, const Geom<T>& g) {
+                                      density_add<KERNEL, T>(acc, g, (double)rec_mass(rj), C);
+                                      ++cnt;
+                                  });
+    finish_density<DIM, T>(i, acc, C, rho_out, rho64, p_out, vel, rp, with_eos);
+    return cnt;
+}
+
+// Summation density over the neighbour lists (or the cell walk).  Without
+// lists (list == nullptr) and with count_pairs, the number of interactions
+// |N(i)| is added to the block's own counter pairs[block] as the list build
+// does otherwise.
 template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> C,
                                                     const uint32_t* __restrict__ skey,
@@ -1457,45 +1520,96 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
     const int blk = xcd_block();
     const int i = blk * kBlock + threadIdx.x;
     uint32_t cnt = 0;
-    if (i < n) {
-        const typename Rec<T>::type ri = pos[i];
-        // The density terms are FP64 in both precisions: the EOS multiplies
-        // density rounding by ~7 B / rho0 before it reaches the forces.
-        double acc = 0.0;
-        for_each_neighbor<DIM, SR, T>(i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list,
-                                      ncnt, cap,
-                                      [&](uint32_t, const typename Rec<T>::type& rj,
-                                          const Geom<T>& g) {
-                                          const double q =
-                                              density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
-                                          acc += (double)rec_mass(rj) *
-                                                 kernel_w<KERNEL, double>(q, C.sigma_d);
-                                          ++cnt;
-                                      });
-        finish_density<DIM, T>(i, acc, C, rho_out, rho64, p_out, vel, rp, with_eos);
+    if (i < n)
+        cnt = density_one<DIM, SR, KERNEL, T>(i, G, C, skey, pos, cstart, cend, n, list, ncnt, cap,
+                                              rho_out, rho64, p_out, vel, rp, with_eos);
+    if (count_pairs) block_count(cnt, pairs, blk);
+}
+
+// Closing epilogue of the momentum pass for slot i with acceleration acc
+// (FP64, per particle, in registers):
+//   kick  = 1: close the step, u = v + dt/2 a (walls: u = 0);
+//   dv: m|u|^2/2 and m u after it (for the diagnostics' block sums);
+//   drift = 1: open the next step (half kick, drift, wrap, hash and count),
+//              leaving v of the next step in u.
+template <int DIM, typename T>
+__device__ __forceinline__ void momentum_close(int i, const T acc[3], bool fluid, const State& S,
+                                               const Grid& G, int kick, int drift, double hdt,
+                                               double dt, uint32_t* __restrict__ key,
+                                               uint32_t* __restrict__ counts,
+                                               uint32_t* __restrict__ flags, bool diag,
+                                               double dv[1 + DIM]) {
+    for (int k = 0; k < DIM; ++k) ((T*)S.a[k])[i] = acc[k];
+    double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
+    {
+#pragma clang fp contract(off)
+        for (int k = 0; k < DIM; ++k) {
+            a[k] = (double)acc[k];
+            const double uk = S.u[k][i];
+            u[k] = kick ? (fluid ? uk + hdt * a[k] : 0.0) : uk;
+        }
+        if (diag) {
+            const double m = S.m[i];
+            double u2 = 0.0;
+            for (int k = 0; k < DIM; ++k) {
+                u2 += u[k] * u[k];
+                dv[1 + k] = m * u[k];
+            }
+            dv[0] = 0.5 * m * u2;
+        }
     }
-    if (!count_pairs) return;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
-    __shared__ uint32_t wcnt[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
-        pairs[blk] += t;
-        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
+    if (drift) {
+        drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags);
+    } else if (kick) {
+        for (int k = 0; k < DIM; ++k) S.u[k][i] = u[k];
     }
 }
 
-// Momentum equation for fluid particles (walls: a = 0):
-//   a_i = g + sum_{j != i} m_j [ -(P_i + P_j) F r_ij
-//                               + 4 nu/(rho_i+rho_j) F |r|^2/(|r|^2 + eta h^2) v_ij ]
-// with F = (dW/dr)/r.  Epilogue (FP64, per particle, in registers):
-//   kick  = 1: close the step, u = v + dt/2 a (walls: u = 0);
-//   diag != 0: per-block partial sums of m|u|^2/2 and m u into diag_part;
-//   drift = 1: open the next step (half kick, drift, wrap, hash and count),
-//              leaving v of the next step in u.
+// Momentum equation of sorted slot i (fluid; walls get a = 0) over its
+// neighbour list (or the cell walk), then momentum_close.
+template <int DIM, int SR, int KERNEL, typename T>
+__device__ __forceinline__ void momentum_one(
+    int i, const Grid& G, const PairConst<T>& C, const uint32_t* __restrict__ skey,
+    const typename Rec<T>::type* __restrict__ pos, const typename Vec4<T>::type* __restrict__ vel,
+    const typename Vec2<T>::type* __restrict__ rp, const uint8_t* __restrict__ type,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, int n,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ ncnt, uint32_t cap,
+    const State& S, int kick, int drift, double hdt, double dt, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ counts, uint32_t* __restrict__ flags, bool diag,
+    double dv[1 + DIM]) {
+    const bool fluid = type[i] == 0;
+    T acc[3] = {T(0), T(0), T(0)};
+    if (fluid) {
+        const typename Rec<T>::type ri = pos[i];
+        const typename Vec4<T>::type vi = vel[i];
+        const typename Vec2<T>::type rpi = load_rp<DIM, T>(vi, rp, (uint32_t)i);
+        T ax = C.g[0], ay = C.g[1], az = C.g[2];
+        struct Pay {
+            typename Vec4<T>::type v;
+            typename Vec2<T>::type rp;
+        };
+        for_each_neighbor_p<DIM, SR, T>(
+            i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
+            [&](uint32_t j) {
+                typename Vec4<T>::type v = vel[j];
+                keep_whole<DIM>(v);
+                return Pay{v, load_rp<DIM, T>(v, rp, j)};
+            },
+            [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
+                momentum_add<DIM, KERNEL, T>(ax, ay, az, g, rec_mass(rj), vi, rpi, pj.v, pj.rp,
+                                             C);
+            });
+        acc[0] = ax;
+        acc[1] = ay;
+        acc[2] = az;
+    }
+    momentum_close<DIM, T>(i, acc, fluid, S, G, kick, drift, hdt, dt, key, counts, flags, diag,
+                           dv);
+}
+
+// Momentum equation for fluid particles (walls: a = 0), over the lists (or
+// the cell walk), with momentum_close as the epilogue; diag_part != 0: per
+// block partial sums of m|u|^2/2 and m u into diag_part.
 template <int DIM, int SR, int KERNEL, typename T>
 __global__ __launch_bounds__(kBlock) void k_momentum(
     int n, Grid G, PairConst<T> C, const uint32_t* __restrict__ skey,
@@ -1510,72 +1624,10 @@ __global__ __launch_bounds__(kBlock) void k_momentum(
     const int i = blk * kBlock + threadIdx.x;
     double dv[1 + DIM];
     for (int q = 0; q <= DIM; ++q) dv[q] = 0.0;
-    if (i < n) {
-        const bool fluid = type[i] == 0;
-        T acc[3] = {T(0), T(0), T(0)};
-        if (fluid) {
-            const typename Rec<T>::type ri = pos[i];
-            const typename Vec4<T>::type vi = vel[i];
-            const typename Vec2<T>::type rpi = load_rp<DIM, T>(vi, rp, (uint32_t)i);
-            T ax = C.g[0], ay = C.g[1], az = C.g[2];
-            struct Pay {
-                typename Vec4<T>::type v;
-                typename Vec2<T>::type rp;
-            };
-            for_each_neighbor_p<DIM, SR, T>(
-                i, G, C, ri, pos, skey, cstart, cend, (uint32_t)n, list, ncnt, cap,
-                [&](uint32_t j) {
-                    typename Vec4<T>::type v = vel[j];
-                    keep_whole<DIM>(v);
-                    return Pay{v, load_rp<DIM, T>(v, rp, j)};
-                },
-                [&](uint32_t, const typename Rec<T>::type& rj, const Pay& pj, const Geom<T>& g) {
-                    // The self pair (j = i) is not skipped: r = 0 and
-                    // v_i - v_i = 0 multiply finite factors (F is finite at
-                    // r = 0 and the viscous factor is taken as 0 there), so
-                    // it adds exactly zero, without a branch in the loop.
-                    const typename Vec4<T>::type vj = pj.v;
-                    const typename Vec2<T>::type rpj = pj.rp;
-                    const T r2 = g.r2;
-                    const T F = kernel_f_r2<KERNEL, T>(r2, C);
-                    const T pres = -(rpi.y + rpj.y) * F;
-                    const T visc = r2 > T(0) ? C.four_nu * F * r2 *
-                                                   p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2))
-                                             : T(0);
-                    const T mj = rec_mass(rj);
-                    ax += mj * (pres * g.d[0] + visc * (vi.x - vj.x));
-                    ay += mj * (pres * g.d[1] + visc * (vi.y - vj.y));
-                    if (DIM == 3) az += mj * (pres * g.d[2] + visc * (vi.z - vj.z));
-                });
-            acc[0] = ax;
-            acc[1] = ay;
-            acc[2] = az;
-        }
-        for (int k = 0; k < DIM; ++k) ((T*)S.a[k])[i] = acc[k];
-        double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
-        {
-#pragma clang fp contract(off)
-            for (int k = 0; k < DIM; ++k) {
-                a[k] = (double)acc[k];
-                const double uk = S.u[k][i];
-                u[k] = kick ? (fluid ? uk + hdt * a[k] : 0.0) : uk;
-            }
-            if (diag_part) {
-                const double m = S.m[i];
-                double u2 = 0.0;
-                for (int k = 0; k < DIM; ++k) {
-                    u2 += u[k] * u[k];
-                    dv[1 + k] = m * u[k];
-                }
-                dv[0] = 0.5 * m * u2;
-            }
-        }
-        if (drift) {
-            drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags);
-        } else if (kick) {
-            for (int k = 0; k < DIM; ++k) S.u[k][i] = u[k];
-        }
-    }
+    if (i < n)
+        momentum_one<DIM, SR, KERNEL, T>(i, G, C, skey, pos, vel, rp, type, cstart, cend, n, list,
+                                         ncnt, cap, S, kick, drift, hdt, dt, key, counts, flags,
+                                         diag_part != nullptr, dv);
     if (diag_part) block_sum4<1 + DIM>(dv, diag_part, blk, gridDim.x);
 }
 
@@ -1698,18 +1750,7 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
         }
     }
     if (diag_part) block_sum4<1 + DIM>(dv, diag_part, blk, gridDim.x);
-    if (!count_pairs) return;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
-    __shared__ uint32_t wcnt[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kBlock / 64; ++w) t += wcnt[w];
-        pairs[blk] += t;
-        if (blk == 0) pairs[-1] = (unsigned long long)gridDim.x;
-    }
+    if (count_pairs) block_count(cnt, pairs, blk);
 }
 
 // Neighbour counts (phase 1) and lists (phase 2) of sph_neighbors.

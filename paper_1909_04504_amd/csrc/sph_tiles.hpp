@@ -1,0 +1,624 @@
+// LDS-staged cell tiles for the 3D mixed-precision pair passes.
+//
+// The cell grid (Sec. 2.2) is cut into boxes of tw x th x td cells.  A
+// workgroup takes one box: its targets are the particles of the box's cells,
+// its candidates those of the union box (the box grown by the stencil reach S
+// on every side), which holds every neighbour of every target.  The union is
+// staged in LDS once per workgroup; the targets then find their neighbours,
+// and later gather their neighbours' records, from LDS instead of from
+// cache-resident global memory.
+//
+//  * Frame: a staged position is the fixed-point offset of the particle from
+//    its cell centre plus its union cell's index times 2^27, so the
+//    separation of two staged particles is the same exact integer as the
+//    cell-relative one of pair_geom; the pair terms are bitwise those of the
+//    global passes.  A float copy, relative to the union centre, filters
+//    candidates outside a band around (2h)^2 (its error is below a tenth of
+//    the band); the exact predicate decides inside the band.
+//  * Walk order: rows (z, y) in stencil order, x cells ascending, slots
+//    ascending -- the order of walk_pairs -- so the lists, their counts and
+//    every sum are those of the global passes.  Rows whose y/z distance from
+//    the target leaves no room for a neighbour are skipped and the others are
+//    clipped in x to the cells the support can reach (with a margin of 1e-4 of
+//    R^2 and of a cell), which drops only candidates the predicate rejects.
+//  * Lists: entries are 16-bit union indices, written by each lane in
+//    octets (16 bytes, one store per eight entries) into tiles of 64 sorted
+//    slots: entry k of slot i at ((i/64) cap/8 + k/8) 64 + i%64 octets.  They
+//    are only meaningful to the tile passes of the same grid.
+//  * Targets the tile passes cannot take -- more neighbours than the list
+//    capacity, or a tile whose union does not fit in LDS (then every target's
+//    count is set to kTileOverflow) -- are left to the fallback kernels, which
+//    walk the cells in global memory with the same arithmetic.  A build that
+//    leaves any such target stores its epoch in the workspace's fallback
+//    word; the fallback kernels exit at once when the word holds another
+//    epoch.
+#pragma once
+
+#include "sph_kernels.hpp"
+
+namespace sph {
+
+constexpr int kTileThreads = 512;                // 8 waves per workgroup
+constexpr int kTileCellsMax = 1024;              // union cells per tile (two per thread)
+constexpr int kTileRowsMax = 64;                 // rows of target cells per tile
+constexpr int kTileCap = 3072;                   // union particles staged in LDS
+constexpr int kTileUnionAxisMax = 12;            // union cells per axis: 12 * 2^27 + 2^29 < 2^31
+constexpr uint32_t kTileOverflow = 0xffffffffu;  // count of a target left to the fallback
+constexpr int kFallbackBlocks = 1024;            // grid of the fallback kernels (grid-stride)
+
+// Tile geometry of one grid (host-computed).
+struct Tiles {
+    int S;                 // stencil reach
+    int tw, th, td;        // tile box, cells
+    int uw, uh, ud;        // union box: tile box + S cells on each side
+    int nt[3];             // tiles per axis
+    int ntiles;
+    int cap;               // staged particles per tile (<= kTileCap)
+    float csf[3];          // cell sizes
+    float inv_csf[3];
+    int cen[3];            // union centre in cells (uw/2, uh/2, ud/2): origin of the float copy
+    float rclip2;          // R^2 (1 + 1e-4): rows farther than this hold no neighbour
+    float clip_pad;        // 1e-4 of a cell: padding of a row's clipped x range
+};
+
+// Per-workgroup bookkeeping in LDS.
+struct TileMeta {
+    uint32_t off[kTileCellsMax + 1];  // union index of each cell's first particle; off[ncu] = total
+    uint32_t gs[kTileCellsMax];       // global slot of each cell's first particle
+    uint32_t tpre[kTileRowsMax + 1];  // targets before each target row
+    uint32_t tg[kTileRowsMax];        // global slot of each target row's first particle
+    int tc[kTileRowsMax];             // union cell of each target row's first cell
+    int ntrows, twc;
+    uint32_t total, ntargets;
+    uint32_t wsum[kTileThreads / 64];
+    uint16_t cellof[kTileCap];        // union cell of each staged particle
+};
+
+// Exclusive scan of two counts per thread (cells 2t, 2t+1) over the
+// workgroup; returns the offset of cell 2t, total in *total.
+__device__ __forceinline__ uint32_t tile_scan2(uint32_t a, uint32_t b, TileMeta& M,
+                                               uint32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t v = a + b;
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) M.wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kTileThreads / 64; ++k) {
+        before += k < w ? M.wsum[k] : 0u;
+        all += M.wsum[k];
+    }
+    *total = all;
+    return before + incl - v;
+}
+
+// Global cell coordinate of union coordinate u along axis k of a tile whose
+// box starts at cell c0; -1 outside a non-periodic grid.
+__device__ __forceinline__ int tile_axis(const Grid& G, int k, int c0, int u, int S) {
+    int c = c0 - S + u;
+    const int nc = G.nc[k];
+    if (c >= 0 && c < nc) return c;
+    if (!G.periodic[k]) return -1;
+    c %= nc;
+    return c < 0 ? c + nc : c;
+}
+
+// Tile origin (first cell) of tile t.
+__device__ __forceinline__ void tile_origin(const Tiles& TL, int t, int c0[3]) {
+    c0[0] = (t % TL.nt[0]) * TL.tw;
+    c0[1] = ((t / TL.nt[0]) % TL.nt[1]) * TL.th;
+    c0[2] = (t / (TL.nt[0] * TL.nt[1])) * TL.td;
+}
+
+// Cell ranges of the union, their scan, and the target rows.  Returns the
+// number of union particles (every thread).
+__device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, const int c0[3],
+                                               const uint32_t* __restrict__ cstart,
+                                               const uint32_t* __restrict__ cend, int n,
+                                               TileMeta& M) {
+    const int ncu = TL.uw * TL.uh * TL.ud;
+    uint32_t cnt[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = 2 * (int)threadIdx.x + q;
+        cnt[q] = 0;
+        if (c < ncu) {
+            const int ux = c % TL.uw, uy = (c / TL.uw) % TL.uh, uz = c / (TL.uw * TL.uh);
+            const int gx = tile_axis(G, 0, c0[0], ux, TL.S);
+            const int gy = tile_axis(G, 1, c0[1], uy, TL.S);
+            const int gz = tile_axis(G, 2, c0[2], uz, TL.S);
+            uint32_t s = 0;
+            if (gx >= 0 && gy >= 0 && gz >= 0) {
+                const uint32_t key = (uint32_t)gx + (uint32_t)G.nc[0] * ((uint32_t)gy + (uint32_t)G.nc[1] * (uint32_t)gz);
+                s = cstart[key];
+                uint32_t e = cend[key];
+                e = e < (uint32_t)n ? e : (uint32_t)n;
+                cnt[q] = e > s ? e - s : 0u;
+            }
+            M.gs[c] = s;
+        }
+    }
+    uint32_t total;
+    const uint32_t o = tile_scan2(cnt[0], cnt[1], M, &total);
+    {
+        const int c = 2 * (int)threadIdx.x;
+        if (c < ncu) M.off[c] = o;
+        if (c + 1 < ncu) M.off[c + 1] = o + cnt[0];
+    }
+    if (threadIdx.x == 0) {
+        M.off[ncu] = total;
+        M.total = total;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // target rows: cells [S, S + twc) of union rows (S + y, S + z)
+        const int twc = min(TL.tw, G.nc[0] - c0[0]);
+        const int thc = min(TL.th, G.nc[1] - c0[1]);
+        const int tdc = min(TL.td, G.nc[2] - c0[2]);
+        int r = 0;
+        uint32_t acc = 0;
+        for (int z = 0; z < tdc; ++z)
+            for (int y = 0; y < thc; ++y) {
+                const int c = TL.S + TL.uw * ((TL.S + y) + TL.uh * (TL.S + z));
+                M.tc[r] = c;
+                M.tg[r] = M.gs[c];
+                M.tpre[r] = acc;
+                acc += M.off[c + twc] - M.off[c];
+                ++r;
+            }
+        M.tpre[r] = acc;
+        M.ntrows = r;
+        M.twc = twc;
+        M.ntargets = acc;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Target t of the tile: its union index, global slot and union cell coords.
+__device__ __forceinline__ void tile_target(const Tiles& TL, const TileMeta& M, uint32_t t,
+                                            uint32_t* ui, uint32_t* gi, int uc[3]) {
+    int r = 0;
+    while (r + 1 < M.ntrows && M.tpre[r + 1] <= t) ++r;
+    const int c = M.tc[r];
+    const uint32_t k = t - M.tpre[r];
+    *ui = M.off[c] + k;
+    *gi = M.tg[r] + k;
+    int x = 0;
+    while (x + 1 < M.twc && M.off[c + x + 1] <= *ui) ++x;
+    uc[0] = TL.S + x;
+    uc[1] = (c / TL.uw) % TL.uh;
+    uc[2] = c / (TL.uw * TL.uh);
+}
+
+// Marks every target of the tile for the fallback (its union does not fit).
+__device__ __forceinline__ void tile_mark_overflow(const TileMeta& M, uint32_t* __restrict__ ncnt) {
+    for (int r = 0; r < M.ntrows; ++r) {
+        const uint32_t len = M.tpre[r + 1] - M.tpre[r];
+        for (uint32_t k = threadIdx.x; k < len; k += kTileThreads) ncnt[M.tg[r] + k] = kTileOverflow;
+    }
+}
+
+// Stages the union's records: store(u, load(j), ux, uy, uz) for union
+// particle u held in global slot j of union cell (ux, uy, uz).  The cell of
+// every union index is noted first, so that each thread then loads four
+// particles at a time (independent loads in flight) at indices t, t + 512, ...
+template <typename Load, typename Store>
+__device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, Load&& load,
+                                           Store&& store) {
+    const int ncu = TL.uw * TL.uh * TL.ud;
+    for (int c = threadIdx.x; c < ncu; c += kTileThreads)
+        for (uint32_t u = M.off[c]; u < M.off[c + 1]; ++u) M.cellof[u] = (uint16_t)c;
+    __syncthreads();
+    const uint32_t total = M.total;
+    using P = decltype(load(0u));
+    for (uint32_t b = threadIdx.x; b < total; b += 4 * kTileThreads) {
+        P v[4];
+        int cq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t u = b + (uint32_t)q * kTileThreads;
+            cq[q] = u < total ? (int)M.cellof[u] : 0;
+            if (u < total) v[q] = load(M.gs[cq[q]] + (u - M.off[cq[q]]));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t u = b + (uint32_t)q * kTileThreads;
+            if (u < total) {
+                const int c = cq[q];
+                store(u, v[q], c % TL.uw, (c / TL.uw) % TL.uh, c / (TL.uw * TL.uh));
+            }
+        }
+    }
+}
+
+// Union-frame record: cell-relative fixed point plus the union cell times 2^27.
+__device__ __forceinline__ int4 tile_rec(const int4& r, int ux, int uy, int uz) {
+    int4 p;
+    p.x = ux * (1 << kFixBits) + r.x;
+    p.y = uy * (1 << kFixBits) + r.y;
+    p.z = uz * (1 << kFixBits) + r.z;
+    p.w = r.w;
+    return p;
+}
+
+// Octet k8 (entries 8 k8 .. 8 k8 + 7) of slot i's list.
+__device__ __forceinline__ size_t tile_octet(uint32_t i, uint32_t cap, uint32_t k8) {
+    return ((size_t)(i >> 6) * (cap >> 3) + k8) * 64 + (i & 63);
+}
+__device__ __forceinline__ uint32_t half_of(const uint4& v, int e) {
+    const uint32_t w = e < 2 ? v.x : (e < 4 ? v.y : (e < 6 ? v.z : v.w));
+    return (e & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
+// Calls body(load(u)) for the cnt entries u of slot i's list, in order.
+// The loads of a full octet's eight entries are issued together and the next
+// octet is fetched meanwhile; the last, partial octet goes entry by entry.
+template <typename Load, typename Body>
+__device__ __forceinline__ void tile_list_loop(const uint4* __restrict__ list, uint32_t i,
+                                               uint32_t cap, uint32_t cnt, Load&& load,
+                                               Body&& body) {
+    using P = decltype(load(0u));
+    const uint32_t nfull = cnt >> 3, rest = cnt & 7u;
+    const uint32_t noct = nfull + (rest ? 1u : 0u);
+    if (noct == 0) return;
+    uint4 nxt = list[tile_octet(i, cap, 0)];
+    for (uint32_t k8 = 0; k8 < nfull; ++k8) {
+        const uint4 cur = nxt;
+        if (k8 + 1 < noct) nxt = list[tile_octet(i, cap, k8 + 1)];
+        P p[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) p[e] = load(half_of(cur, e));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) body(p[e]);
+    }
+    if (rest) {
+#pragma unroll
+        for (int e = 0; e < 7; ++e)
+            if ((uint32_t)e < rest) body(load(half_of(nxt, e)));
+    }
+}
+
+// Per-thread FP64 values summed over the workgroup (wave butterflies, then
+// the waves in order) into part[q * stride + b].
+template <int NV>
+__device__ __forceinline__ void tile_block_sum(double v[NV], double* __restrict__ part, int b,
+                                               int stride) {
+    __shared__ double sh[NV][kTileThreads / 64];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+        v[q] = x;
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < NV; ++q) sh[q][threadIdx.x >> 6] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < kTileThreads / 64; ++w) s += sh[q][w];
+            part[(int64_t)q * stride + b] = s;
+        }
+}
+
+// Workgroup sum of a per-thread count into the tile's interaction counter.
+__device__ __forceinline__ void tile_count(uint32_t cnt, unsigned long long* __restrict__ pairs,
+                                           int blk) {
+    __shared__ uint32_t wc[kTileThreads / 64];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kTileThreads / 64; ++w) t += wc[w];
+        add_pairs(pairs, blk, t);
+    }
+}
+
+// Neighbour lists of the tile's targets: ncnt[i] = |N(i)|, entries while the
+// count is within cap; targets with more are left to the fallback, as are all
+// targets of a tile whose union exceeds cap_union.  count_pairs: the
+// interactions of the counted targets go to the tile's counter.  Only the
+// float copy of the union is staged (so that two workgroups share a CU); the
+// exact predicate inside the band reads the candidate's record from global
+// memory.  Entries are appended without branches: every candidate is written
+// at the next free place of a 16-entry ring and the count advances only for
+// accepted ones; a completed octet is stored at once.
+template <int S>
+__global__ __launch_bounds__(kTileThreads) void k_tile_build(
+    int n, Grid G, PairConst<float> C, Tiles TL, int cap_union, const int4* __restrict__ pos,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, uint32_t cap,
+    uint4* __restrict__ list, uint32_t* __restrict__ ncnt, int count_pairs,
+    unsigned long long* __restrict__ pairs, uint32_t epoch, uint32_t* __restrict__ fallback) {
+    __shared__ TileMeta M;
+    __shared__ float4 Pf[kTileCap + 8];  // + the candidates read past a row's end
+    __shared__ uint4 ring[kTileThreads][2];
+    const int blk = xcd_block();
+    int c0[3];
+    tile_origin(TL, blk, c0);
+    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
+    if (total > (uint32_t)cap_union) {
+        tile_mark_overflow(M, ncnt);
+        if (threadIdx.x == 0 && M.ntargets) *fallback = epoch;
+        return;
+    }
+    tile_stage(TL, M, [&](uint32_t j) { return pos[j]; },
+               [&](uint32_t u, const int4& r, int ux, int uy, int uz) {
+                   const int4 p = tile_rec(r, ux, uy, uz);
+                   float4 f;
+                   f.x = (float)(p.x - TL.cen[0] * (1 << kFixBits)) * C.fix_scale_f[0];
+                   f.y = (float)(p.y - TL.cen[1] * (1 << kFixBits)) * C.fix_scale_f[1];
+                   f.z = (float)(p.z - TL.cen[2] * (1 << kFixBits)) * C.fix_scale_f[2];
+                   f.w = 0.f;
+                   Pf[u] = f;
+               });
+    __syncthreads();
+    uint16_t* my = (uint16_t*)ring[threadIdx.x];
+    uint32_t counted = 0;
+    bool need_fb = false;
+    const float cxf = (float)TL.cen[0], cyf = (float)TL.cen[1], czf = (float)TL.cen[2];
+    const int ncu_w = TL.uw, ncu_wh = TL.uw * TL.uh;
+    for (uint32_t t = threadIdx.x; t < M.ntargets; t += kTileThreads) {
+        uint32_t ui, i;
+        int uc[3];
+        tile_target(TL, M, t, &ui, &i, uc);
+        const float4 pf = Pf[ui];
+        const int4 pi = tile_rec(pos[i], uc[0], uc[1], uc[2]);
+        // rows are clipped only for a target inside its cell (a particle
+        // clamped into an edge cell from outside a non-periodic box walks
+        // whole rows, as walk_pairs does)
+        const int half = 1 << (kFixBits - 1);
+        const bool clip = abs(pi.x - uc[0] * (1 << kFixBits)) <= half &&
+                          abs(pi.y - uc[1] * (1 << kFixBits)) <= half &&
+                          abs(pi.z - uc[2] * (1 << kFixBits)) <= half;
+        // exact predicate on the integer separation (candidate's record from
+        // global memory, in the union frame)
+        auto exact = [&](uint32_t u) {
+            const int c = M.cellof[u];
+            const int4 pj = tile_rec(pos[M.gs[c] + (u - M.off[c])], c % ncu_w,
+                                     (c / ncu_w) % TL.uh, c / ncu_wh);
+            const Geom<float> g = pair_geom<3>(pi, pj, 0, 0, 0, 0, 0, 0, C);
+            return geom_r2d(g, C) < C.R2_d;
+        };
+        uint32_t cnt = 0;
+        // the (2S+1)^2 stencil rows in walk order; a loop, not unrolled, so the
+        // kernel's code stays small enough for the instruction cache
+        constexpr int NR = 2 * S + 1;
+#pragma unroll 1
+        for (int row = 0; row < NR * NR; ++row) {
+            const int uy = uc[1] + row % NR - S, uz = uc[2] + row / NR - S;
+            const float dz = fmaxf(fabsf(pf.z - ((float)uz - czf) * TL.csf[2]) - 0.5f * TL.csf[2], 0.f);
+            const float dy = fmaxf(fabsf(pf.y - ((float)uy - cyf) * TL.csf[1]) - 0.5f * TL.csf[1], 0.f);
+            const float w2 = TL.rclip2 - dy * dy - dz * dz;
+            if (clip && !(w2 > 0.f)) continue;
+            int xa = uc[0] - S, xb = uc[0] + S;
+            if (clip) {
+                const float w = __builtin_amdgcn_sqrtf(w2) + TL.clip_pad;
+                xa = max(xa, (int)floorf((pf.x - w) * TL.inv_csf[0] + cxf + 0.5f));
+                xb = min(xb, (int)floorf((pf.x + w) * TL.inv_csf[0] + cxf + 0.5f));
+                if (xa > xb) continue;
+            }
+            const int rowc = TL.uw * (uy + TL.uh * uz);
+            const uint32_t ua = M.off[rowc + xa], ue = M.off[rowc + xb + 1];
+            // candidates four at a time, the next four loaded while these
+            // are tested; those past the row's end (read from the padding or
+            // the next row) are infinitely far
+            uint32_t u = ua;
+            float4 c[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = Pf[u + q];
+#pragma unroll 1
+            for (; u < ue; u += 4) {
+                bool acc[4], band[4];
+                bool anyband = false;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float dx = pf.x - c[q].x, ddy = pf.y - c[q].y, ddz = pf.z - c[q].z;
+                    const float r2 =
+                        u + q < ue ? dx * dx + ddy * ddy + ddz * ddz : __builtin_huge_valf();
+                    acc[q] = r2 < C.R2_lo;
+                    band[q] = fabsf(r2 - C.R2_mid) < C.R2_w;
+                    anyband |= band[q];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) c[q] = Pf[u + 4 + q];
+                if (__builtin_amdgcn_ballot_w64(anyband)) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (band[q]) acc[q] = exact(u + q);
+                }
+                const uint32_t c_in = cnt;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    my[cnt & 15] = (uint16_t)(u + q);
+                    cnt += acc[q] ? 1u : 0u;
+                }
+                // an octet completed (at most one per group of four)
+                if ((cnt ^ c_in) & ~7u) {
+                    const uint32_t k8 = c_in >> 3;
+                    if (k8 < (cap >> 3)) list[tile_octet(i, cap, k8)] = ring[threadIdx.x][k8 & 1];
+                }
+            }
+        }
+        if (cnt <= cap && (cnt & 7)) list[tile_octet(i, cap, cnt >> 3)] = ring[threadIdx.x][(cnt >> 3) & 1];
+        ncnt[i] = cnt;
+        counted += cnt;
+        need_fb |= cnt > cap;
+    }
+    if (__syncthreads_or(need_fb) && threadIdx.x == 0) *fallback = epoch;
+    if (count_pairs) tile_count(counted, pairs, blk);
+}
+
+// Summation density (eq. 2), and with_eos the Tait EOS (eq. eos), of the
+// tile's targets with complete lists (as k_density), over the union's
+// position records staged in LDS.
+template <int S, int KERNEL>
+__global__ __launch_bounds__(kTileThreads) void k_tile_density(
+    int n, Grid G, PairConst<float> C, Tiles TL, int cap_union, const int4* __restrict__ pos,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend, uint32_t cap,
+    const uint4* __restrict__ list, const uint32_t* __restrict__ ncnt,
+    float* __restrict__ rho_out, float* __restrict__ p_out, float4* __restrict__ vel,
+    float2* __restrict__ rp, int with_eos) {
+    __shared__ TileMeta M;
+    __shared__ int4 Pi[kTileCap];
+    const int blk = xcd_block();
+    int c0[3];
+    tile_origin(TL, blk, c0);
+    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
+    if (total > (uint32_t)cap_union) return;  // every target is the fallback's
+    tile_stage(TL, M, [&](uint32_t j) { return pos[j]; },
+               [&](uint32_t u, const int4& r, int ux, int uy, int uz) {
+                   Pi[u] = tile_rec(r, ux, uy, uz);
+               });
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < M.ntargets; t += kTileThreads) {
+        uint32_t ui, i;
+        int uc[3];
+        tile_target(TL, M, t, &ui, &i, uc);
+        const uint32_t cnt = ncnt[i];
+        if (cnt > cap) continue;  // the fallback's
+        const int4 pi = Pi[ui];
+        double acc = 0.0;
+        tile_list_loop(list, i, cap, cnt, [&](uint32_t u) { return Pi[u]; },
+                       [&](const int4& pj) {
+                           const Geom<float> g = pair_geom<3>(pi, pj, 0, 0, 0, 0, 0, 0, C);
+                           density_add<KERNEL, float>(acc, g, (double)rec_mass(pj), C);
+                       });
+        finish_density<3, float>((int)i, acc, C, rho_out, 0, p_out, vel, rp, with_eos);
+    }
+}
+
+// Momentum equation (as k_momentum) of the tile's targets whose lists are
+// complete, over the union's position, velocity and (rho, P) records staged
+// in LDS, with momentum_close as the epilogue; per-tile partial sums of the
+// diagnostics into diag_part[q * stride + tile].
+template <int S, int KERNEL>
+__global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
+    int n, Grid G, PairConst<float> C, Tiles TL, int cap_union, const int4* __restrict__ pos,
+    const float4* __restrict__ vel, const float2* __restrict__ rp,
+    const uint8_t* __restrict__ type, const uint32_t* __restrict__ cstart,
+    const uint32_t* __restrict__ cend, uint32_t cap, const uint4* __restrict__ list,
+    const uint32_t* __restrict__ ncnt, State St, int kick, int drift, double hdt, double dt,
+    uint32_t* __restrict__ key, uint32_t* __restrict__ counts, uint32_t* __restrict__ flags,
+    double* __restrict__ diag_part, int stride) {
+    __shared__ TileMeta M;
+    __shared__ int4 Pi[kTileCap];
+    __shared__ float4 V[kTileCap];
+    __shared__ float2 RP[kTileCap];
+    const int blk = xcd_block();
+    int c0[3];
+    tile_origin(TL, blk, c0);
+    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
+    double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool fits = total <= (uint32_t)cap_union;
+    if (fits) {
+        struct Rc {
+            int4 p;
+            float4 v;
+            float2 rp;
+        };
+        tile_stage(TL, M, [&](uint32_t j) { return Rc{pos[j], vel[j], rp[j]}; },
+                   [&](uint32_t u, const Rc& r, int ux, int uy, int uz) {
+                       Pi[u] = tile_rec(r.p, ux, uy, uz);
+                       V[u] = r.v;
+                       RP[u] = r.rp;
+                   });
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < M.ntargets; t += kTileThreads) {
+            uint32_t ui, i;
+            int uc[3];
+            tile_target(TL, M, t, &ui, &i, uc);
+            const uint32_t cnt = ncnt[i];
+            if (cnt > cap) continue;  // the fallback's
+            const bool fluid = type[i] == 0;
+            float acc[3] = {0.f, 0.f, 0.f};
+            if (fluid) {
+                const int4 pi = Pi[ui];
+                const float4 vi = V[ui];
+                const float2 rpi = RP[ui];
+                float ax = C.g[0], ay = C.g[1], az = C.g[2];
+                struct Nb {
+                    int4 p;
+                    float4 v;
+                    float2 rp;
+                };
+                tile_list_loop(list, i, cap, cnt, [&](uint32_t u) { return Nb{Pi[u], V[u], RP[u]}; },
+                               [&](const Nb& b) {
+                                   const Geom<float> g =
+                                       pair_geom<3>(pi, b.p, 0, 0, 0, 0, 0, 0, C);
+                                   momentum_add<3, KERNEL, float>(ax, ay, az, g, rec_mass(b.p),
+                                                                  vi, rpi, b.v, b.rp, C);
+                               });
+                acc[0] = ax;
+                acc[1] = ay;
+                acc[2] = az;
+            }
+            double dv[4] = {0.0, 0.0, 0.0, 0.0};
+            momentum_close<3, float>((int)i, acc, fluid, St, G, kick, drift, hdt, dt, key, counts,
+                                     flags, diag_part != nullptr, dv);
+            for (int q = 0; q < 4; ++q) dsum[q] += dv[q];
+        }
+    }
+    if (diag_part) tile_block_sum<4>(dsum, diag_part, blk, stride);
+}
+
+// Fallback density: the targets the tile build left (count above cap, or
+// kTileOverflow), by the cell walk in global memory (density_one); only the
+// kTileOverflow ones are counted (the build counted the others).
+template <int S, int KERNEL>
+__global__ __launch_bounds__(kBlock) void k_tile_fallback_density(
+    int n, Grid G, PairConst<float> C, const uint32_t* __restrict__ skey,
+    const int4* __restrict__ pos, const uint32_t* __restrict__ cstart,
+    const uint32_t* __restrict__ cend, const uint32_t* __restrict__ ncnt, uint32_t cap,
+    float* __restrict__ rho_out, float* __restrict__ p_out, float4* __restrict__ vel,
+    float2* __restrict__ rp, int with_eos, int count_pairs, unsigned long long* __restrict__ pairs,
+    uint32_t epoch, const uint32_t* __restrict__ fallback) {
+    if (*fallback != epoch) return;
+    uint32_t counted = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const uint32_t c = ncnt[i];
+        if (c <= cap) continue;
+        // a null list makes density_one walk the cells
+        const uint32_t k = density_one<3, S, KERNEL, float>(i, G, C, skey, pos, cstart, cend, n,
+                                                            nullptr, ncnt, cap, rho_out, 0, p_out,
+                                                            vel, rp, with_eos);
+        if (c == kTileOverflow) counted += k;
+    }
+    if (count_pairs) block_count(counted, pairs, blockIdx.x);
+}
+
+// Fallback momentum, as k_tile_fallback_density; diagnostics partials of its
+// blocks at diag_part[q * stride + b] (zeros when there is nothing to do).
+template <int S, int KERNEL>
+__global__ __launch_bounds__(kBlock) void k_tile_fallback_momentum(
+    int n, Grid G, PairConst<float> C, const uint32_t* __restrict__ skey,
+    const int4* __restrict__ pos, const float4* __restrict__ vel, const float2* __restrict__ rp,
+    const uint8_t* __restrict__ type, const uint32_t* __restrict__ cstart,
+    const uint32_t* __restrict__ cend, const uint32_t* __restrict__ ncnt, uint32_t cap, State St,
+    int kick, int drift, double hdt, double dt, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ counts, uint32_t* __restrict__ flags, double* __restrict__ diag_part,
+    int stride, uint32_t epoch, const uint32_t* __restrict__ fallback) {
+    double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+    if (*fallback == epoch) {
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+            if (ncnt[i] <= cap) continue;
+            double dv[4] = {0.0, 0.0, 0.0, 0.0};
+            momentum_one<3, S, KERNEL, float>(i, G, C, skey, pos, vel, rp, type, cstart, cend, n,
+                                              nullptr, ncnt, cap, St, kick, drift, hdt, dt, key,
+                                              counts, flags, diag_part != nullptr, dv);
+            for (int q = 0; q < 4; ++q) dsum[q] += dv[q];
+        }
+    }
+    if (diag_part) block_sum4<4>(dsum, diag_part, blockIdx.x, stride);
+}
+
+}  // namespace sph

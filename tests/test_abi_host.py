@@ -38,8 +38,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # 8 int32 + 6 double + 9 double + 2 int32 (scheme, integrator)
-    assert ctypes.sizeof(sph.Params) == 8 * 4 + 15 * 8 + 2 * 4
+    # 8 int32 + 6 double + 9 double + 3 int32 (scheme, integrator, pair_tiles) + padding
+    assert ctypes.sizeof(sph.Params) == 8 * 4 + 15 * 8 + 4 * 4
     # n, x/u/a (3 pointers each), rho, p, m, type, id, arho
     assert ctypes.sizeof(sph.Particles) == 8 + 9 * 8 + 6 * 8
 
