@@ -51,7 +51,12 @@ FLOPS_PER_PAIR = {
     # gradient factor and the mass, and the accumulation
     ("cont_momentum", 2): 40, ("cont_momentum", 3): 50,
 }
-PAIR_KERNELS = ("nlist", "density", "momentum", "cont_momentum")
+PAIR_KERNELS = ("nlist", "density", "momentum", "cont_momentum", "tile_build", "tile_density",
+                "tile_momentum")
+# bytes per list entry: 32-bit global lists, 16-bit tile lists (union indices)
+ENTRY_BYTES = {"nlist": 4, "density": 4, "momentum": 4, "cont_momentum": 4, "tile_build": 2,
+               "tile_density": 2, "tile_momentum": 2}
+FLOPS_PER_PAIR.update({("tile_density", 3): 20, ("tile_momentum", 3): 42})
 KERNEL_NAMES = {0: "cubic spline", 1: "Wendland C2", 2: "quintic spline"}
 # Neighbour-list build: per candidate pair tested (every particle of the
 # stencil cells of i's cell): the separation (dim), |r|^2 (2 dim - 1).
@@ -68,6 +73,15 @@ def bytes_per_particle(kernel: str, dim: int, tsize: int, continuity: bool = Fal
     if kernel == "nlist":
         # in: record, key; out: neighbour count
         return R + 4 + 4
+    if kernel == "tile_build":
+        # in: record, cell range; out: neighbour count
+        return R + 4 + 4
+    if kernel == "tile_density":
+        # in: record, count; out: rho, p, (rho, P)
+        return R + 4 + 2 * T + 2 * T
+    if kernel == "tile_momentum":
+        # as momentum
+        return R + 4 + 4 * T + 2 * T + 1 + 8 * d + d * T + 8 * d + 4
     if kernel == "density":
         # in: record, count; out: rho, p, (rho, P)
         return R + 4 + 2 * T + 2 * T
@@ -93,9 +107,11 @@ def bytes_per_particle(kernel: str, dim: int, tsize: int, continuity: bool = Fal
 
 
 def source_digest() -> str:
+    """Digest of the library's device and launch sources (the traffic of a
+    profiled kernel is used only while it matches)."""
     h = hashlib.sha256()
-    for f in ("paper_1909_04504_amd/csrc/sph_kernels.hpp", "paper_1909_04504_amd/csrc/sph.hip"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in ("sph_kernels.hpp", "sph_tiles.hpp", "sph_adjoint.hpp", "sph_engine.hpp", "sph.hip"):
+        with open(os.path.join(ROOT, "paper_1909_04504_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -205,12 +221,16 @@ def roofline(res, wl, prec, steps, tests=None):
     nbytes = bytes_per_particle(dom, dim, tsize, wl.params.scheme == 1) * n
     flops = None
     if dom in PAIR_KERNELS:
-        nbytes += 4 * inter_per_launch  # the neighbour lists, written or read once
-        if dom == "nlist":
+        # the neighbour lists, written or read once
+        nbytes += ENTRY_BYTES[dom] * inter_per_launch
+        if dom in ("nlist", "tile_build"):
+            # the predicate on every candidate of the (2S+1)^d stencil cells
+            # (the tiled build skips the cells beyond the support's reach, so
+            # it evaluates fewer)
             flops = FLOPS_PER_TEST[dim] * tests
         else:
             # the momentum passes do no arithmetic for the self pair
-            pairs = inter_per_launch if dom == "density" else inter_per_launch - n
+            pairs = inter_per_launch if dom in ("density", "tile_density") else inter_per_launch - n
             flops = FLOPS_PER_PAIR[(dom, dim)] * pairs
     hbm_ach = nbytes / avg_s / 1e9
     out = {"kernel": dom, "avg_launch_us": kus[dom], "bytes_per_launch": nbytes,
@@ -228,7 +248,7 @@ def roofline(res, wl, prec, steps, tests=None):
         out.update({"bound": "alu", **out["alu"]})
     else:
         out.update({"bound": "hbm", **out["hbm"]})
-    if dom == "nlist":
+    if dom in ("nlist", "tile_build"):
         out["pair_tests_per_launch"] = tests
     out["traffic"] = traffic_from_profile(dom, wl.name)
     return out

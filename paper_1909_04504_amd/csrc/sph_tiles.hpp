@@ -209,6 +209,7 @@ __device__ __forceinline__ void tile_mark_overflow(const TileMeta& M, uint32_t* 
 // particle u held in global slot j of union cell (ux, uy, uz).  The cell of
 // every union index is noted first, so that each thread then loads four
 // particles at a time (independent loads in flight) at indices t, t + 512, ...
+// (kTileCap <= 8 * kTileThreads: a single round)
 template <typename Load, typename Store>
 __device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, Load&& load,
                                            Store&& store) {
@@ -218,17 +219,19 @@ __device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, Load&& 
     __syncthreads();
     const uint32_t total = M.total;
     using P = decltype(load(0u));
-    for (uint32_t b = threadIdx.x; b < total; b += 4 * kTileThreads) {
-        P v[4];
-        int cq[4];
+    constexpr int kQ = (kTileCap + kTileThreads - 1) / kTileThreads;
+    static_assert(kQ <= 8, "staging registers");
+    for (uint32_t b = threadIdx.x; b < total; b += kQ * kTileThreads) {
+        P v[kQ];
+        int cq[kQ];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kQ; ++q) {
             const uint32_t u = b + (uint32_t)q * kTileThreads;
             cq[q] = u < total ? (int)M.cellof[u] : 0;
             if (u < total) v[q] = load(M.gs[cq[q]] + (u - M.off[cq[q]]));
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kQ; ++q) {
             const uint32_t u = b + (uint32_t)q * kTileThreads;
             if (u < total) {
                 const int c = cq[q];
@@ -258,8 +261,9 @@ __device__ __forceinline__ uint32_t half_of(const uint4& v, int e) {
 }
 
 // Calls body(load(u)) for the cnt entries u of slot i's list, in order.
-// The loads of a full octet's eight entries are issued together and the next
-// octet is fetched meanwhile; the last, partial octet goes entry by entry.
+// The loads of a full octet's eight entries are issued together and the
+// octets two ahead are fetched meanwhile; the last, partial octet goes entry
+// by entry.
 template <typename Load, typename Body>
 __device__ __forceinline__ void tile_list_loop(const uint4* __restrict__ list, uint32_t i,
                                                uint32_t cap, uint32_t cnt, Load&& load,
@@ -269,9 +273,12 @@ __device__ __forceinline__ void tile_list_loop(const uint4* __restrict__ list, u
     const uint32_t noct = nfull + (rest ? 1u : 0u);
     if (noct == 0) return;
     uint4 nxt = list[tile_octet(i, cap, 0)];
+    uint4 nxt2 = nxt;
+    if (noct > 1) nxt2 = list[tile_octet(i, cap, 1)];
     for (uint32_t k8 = 0; k8 < nfull; ++k8) {
         const uint4 cur = nxt;
-        if (k8 + 1 < noct) nxt = list[tile_octet(i, cap, k8 + 1)];
+        nxt = nxt2;
+        if (k8 + 2 < noct) nxt2 = list[tile_octet(i, cap, k8 + 2)];
         P p[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) p[e] = load(half_of(cur, e));
@@ -418,29 +425,35 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
             for (int q = 0; q < 4; ++q) c[q] = Pf[u + q];
 #pragma unroll 1
             for (; u < ue; u += 4) {
-                bool acc[4], band[4];
-                bool anyband = false;
+                const uint32_t lim = ue - u;  // candidates left in the row
+                float r2[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const float dx = pf.x - c[q].x, ddy = pf.y - c[q].y, ddz = pf.z - c[q].z;
-                    const float r2 =
-                        u + q < ue ? dx * dx + ddy * ddy + ddz * ddz : __builtin_huge_valf();
-                    acc[q] = r2 < C.R2_lo;
-                    band[q] = fabsf(r2 - C.R2_mid) < C.R2_w;
-                    anyband |= band[q];
+                    r2[q] = dx * dx + ddy * ddy + ddz * ddz;
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) c[q] = Pf[u + 4 + q];
+                uint32_t acc[4];
+                bool band[4];
+                bool anyband = false;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float x = (uint32_t)q < lim ? r2[q] : __builtin_huge_valf();
+                    acc[q] = x < C.R2_lo ? 1u : 0u;
+                    band[q] = fabsf(x - C.R2_mid) < C.R2_w;
+                    anyband |= band[q];
+                }
                 if (__builtin_amdgcn_ballot_w64(anyband)) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (band[q]) acc[q] = exact(u + q);
+                        if (band[q]) acc[q] = exact(u + q) ? 1u : 0u;
                 }
                 const uint32_t c_in = cnt;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     my[cnt & 15] = (uint16_t)(u + q);
-                    cnt += acc[q] ? 1u : 0u;
+                    cnt += acc[q];
                 }
                 // an octet completed (at most one per group of four)
                 if ((cnt ^ c_in) & ~7u) {
