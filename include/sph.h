@@ -260,6 +260,24 @@ int sph_read_interactions(void* ws, size_t ws_bytes, int64_t* total, int reset, 
 int sph_timer_enable(int on);
 int sph_timer_read(int nslots, const char** names, double* ms, int64_t* launches, int reset);
 
+/* Bytes of the static device scratch of sph_step_noalloc (one copy per device,
+ * held until the process ends). */
+#define SPH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* sph_step without a caller workspace, for callers that cannot allocate
+ * device memory (code under graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the workspace is a static device array of
+ * SPH_NOALLOC_SCRATCH_BYTES bytes per device, found with hipGetSymbolAddress
+ * on the first call on each device.  Same arguments and results as sph_step
+ * otherwise; the caller still provides the particle arrays and diag.
+ * Allocates nothing.  Returns SPH_EWORKSPACE when sph_workspace_bytes(prm, n,
+ * 0) exceeds SPH_NOALLOC_SCRATCH_BYTES.  Every call on a device shares that
+ * device's array, which keeps the last call's contents: each call clears its
+ * flag words and interaction counters first (device-detected conditions are
+ * not reported), and calls that overlap on one device race. */
+int sph_step_noalloc(const sph_params* prm, sph_particles* pa, int64_t nsteps, int prime_accel,
+                     double* diag, void* stream);
+
 /* Synchronises the stream and returns SPH_OK, or the first device-detected
  * condition since the last call (SPH_ENONFINITE, then SPH_EDOMAIN), and
  * clears the flags. */

@@ -21,6 +21,7 @@ from . import build as _build
 SPH_OK, SPH_EINVAL, SPH_EWORKSPACE, SPH_ECAPACITY = 0, -1, -2, -3
 SPH_EDOMAIN, SPH_ENONFINITE, SPH_EDEVICE = -4, -5, -6
 FP64, FP32_MIXED = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SPH_NOALLOC_SCRATCH_BYTES of sph.h
 SUMMATION, CONTINUITY = 0, 1  # sph_params.scheme
 PREDICTOR_CORRECTOR, EULER = 0, 1  # sph_params.integrator
 
@@ -52,7 +53,7 @@ class Particles(ctypes.Structure):
 EXPORTED = ("sph_grid", "sph_workspace_bytes", "sph_bin_sort", "sph_neighbors", "sph_density",
             "sph_eos", "sph_momentum", "sph_step", "sph_step_backward", "sph_accel_backward",
             "sph_check", "sph_last_error", "sph_read_interactions", "sph_timer_enable",
-            "sph_timer_read")
+            "sph_timer_read", "sph_step_noalloc")
 
 _lib = None
 
@@ -75,6 +76,7 @@ def lib():
         L.sph_eos.argtypes = [_P, _P, _P]
         L.sph_momentum.argtypes = [_P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_step.argtypes = [_P, _P, _i64, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]
+        L.sph_step_noalloc.argtypes = [_P, _P, _i64, ctypes.c_int, _P, _P]
         L.sph_step_backward.argtypes = [_P, _P, _i64, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_accel_backward.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_check.argtypes = [_P, ctypes.c_size_t, _P]
@@ -269,6 +271,14 @@ def step(prm, dp, nsteps: int, ws, prime: bool = True, diag: Optional[torch.Tens
     _rc(lib().sph_step(ctypes.byref(prm), ctypes.byref(s), nsteps, 1 if prime else 0,
                        ws.data_ptr(), ws.numel(), diag.data_ptr() if diag is not None else None,
                        _stream(stream)))
+
+
+def step_noalloc(prm, dp, nsteps: int, prime: bool = True, diag: Optional[torch.Tensor] = None,
+                 stream=None):
+    """sph_step_noalloc: sph_step on the library's static device scratch."""
+    s = dp.struct(prm)
+    _rc(lib().sph_step_noalloc(ctypes.byref(prm), ctypes.byref(s), nsteps, 1 if prime else 0,
+                               diag.data_ptr() if diag is not None else None, _stream(stream)))
 
 
 def step_backward(prm, ckpt: DeviceParticles, k: int, lam_in, lam_out, dJ_dnu, ws, stream=None):

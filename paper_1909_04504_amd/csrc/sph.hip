@@ -5,6 +5,36 @@
 
 using namespace sph_host;
 
+#include <mutex>
+
+// Static workspace of sph_step_noalloc: one copy per device.  Host code never
+// passes this name to a kernel (in host code it is a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress returns for the current
+// device, kept per device below.
+static __device__ __align__(256) unsigned char scratch[SPH_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once).
+int scratch_address(void** out) {
+    int dev = 0;
+    SPH_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPH_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        SPH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SPH_EDEVICE, "no device address for the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPH_OK;
+}
+}  // namespace
+
 #define SPH_EXTERN_API(D, K, TT) extern template struct sph_host::Api<D, K, TT>;
 SPH_FOR_EACH_COMBO(SPH_EXTERN_API)
 #undef SPH_EXTERN_API
@@ -110,6 +140,34 @@ int sph_step(const sph_params* prm, sph_particles* pa, int64_t nsteps, int prime
     if (prime_accel != 0 && prime_accel != 1) return fail(SPH_EINVAL, "prime_accel must be 0 or 1");
     return dispatch(prm, [&](auto A) {
         return decltype(A)::step(prm, pa, nsteps, prime_accel, ws, ws_bytes, diag, stream);
+    });
+}
+
+int sph_step_noalloc(const sph_params* prm, sph_particles* pa, int64_t nsteps, int prime_accel,
+                     double* diag, void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, true));
+    SPH_TRY(check_particles(prm, pa));
+    if (nsteps < 0) return fail(SPH_EINVAL, "nsteps must be >= 0");
+    if (prime_accel != 0 && prime_accel != 1) return fail(SPH_EINVAL, "prime_accel must be 0 or 1");
+    sph::Grid G;
+    int64_t ncells;
+    SPH_TRY(make_grid(prm, &G, &ncells));
+    const Layout L = make_layout(prm, G, pa->n, ncells, 0);
+    if (L.bytes > SPH_NOALLOC_SCRATCH_BYTES)
+        return fail(SPH_EWORKSPACE, "the step needs %zu bytes of workspace, the static scratch holds %zu",
+                    L.bytes, (size_t)SPH_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    SPH_TRY(scratch_address(&ws));
+    // the flag words and interaction counters start at zero (a fill kernel,
+    // so that the call can be captured into a graph)
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t words = (int64_t)(L.counts / 4);
+    launch(K_FILL, sph::k_fill_u32, blocks_for(words), st, words, 0u, (uint32_t*)ws);
+    SPH_TRY(launch_check("k_fill_u32"));
+    return dispatch(prm, [&](auto A) {
+        return decltype(A)::step(prm, pa, nsteps, prime_accel, ws, (size_t)SPH_NOALLOC_SCRATCH_BYTES,
+                                 diag, stream);
     });
 }
 

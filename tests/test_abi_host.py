@@ -216,3 +216,13 @@ def test_binding_layout_matches_the_c_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_noalloc_scratch_size_mirrors_header():
+    """The binding's NOALLOC_SCRATCH_BYTES is the header's
+    SPH_NOALLOC_SCRATCH_BYTES (64 MiB)."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "sph.h")).read()
+    m = re.search(r"#define SPH_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m
+    assert sph.NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
