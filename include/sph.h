@@ -233,6 +233,14 @@ int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t 
                       const double* lam_in, double* lam_out, double* dJ_dnu, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* Adjoint seed of the kinetic-energy objective J = scale sum_i m_i |u_i|^2 / 2
+ * at the state pa (the end state of a rollout, as sph_step leaves it): writes
+ * lam (3*dim arrays of n doubles, the [lam_x][lam_u][lam_a] layout of
+ * sph_step_backward) with lam_x = 0, lam_u = scale m u, lam_a = 0.  Not part
+ * of the paper (the differentiation pattern of this library). */
+int sph_ke_seed(const sph_params* prm, const sph_particles* pa, double scale, double* lam,
+                void* stream);
+
 /* Adjoint of the acceleration evaluation a = A(x, u; nu) at the state `st`
  * (sorted or not): given lam_a (dim arrays of n doubles), ADDS (dA/dx)^T lam_a
  * to lam_x, (dA/du)^T lam_a to lam_u and (dA/dnu)^T lam_a to *dJ_dnu.

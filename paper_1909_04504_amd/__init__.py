@@ -53,7 +53,7 @@ class Particles(ctypes.Structure):
 EXPORTED = ("sph_grid", "sph_workspace_bytes", "sph_bin_sort", "sph_neighbors", "sph_density",
             "sph_eos", "sph_momentum", "sph_step", "sph_step_backward", "sph_accel_backward",
             "sph_check", "sph_last_error", "sph_read_interactions", "sph_timer_enable",
-            "sph_timer_read", "sph_step_noalloc")
+            "sph_timer_read", "sph_step_noalloc", "sph_ke_seed")
 
 _lib = None
 
@@ -77,6 +77,7 @@ def lib():
         L.sph_momentum.argtypes = [_P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_step.argtypes = [_P, _P, _i64, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]
         L.sph_step_noalloc.argtypes = [_P, _P, _i64, ctypes.c_int, _P, _P]
+        L.sph_ke_seed.argtypes = [_P, _P, ctypes.c_double, _P, _P]
         L.sph_step_backward.argtypes = [_P, _P, _i64, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_accel_backward.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.sph_check.argtypes = [_P, ctypes.c_size_t, _P]
@@ -279,6 +280,13 @@ def step_noalloc(prm, dp, nsteps: int, prime: bool = True, diag: Optional[torch.
     s = dp.struct(prm)
     _rc(lib().sph_step_noalloc(ctypes.byref(prm), ctypes.byref(s), nsteps, 1 if prime else 0,
                                diag.data_ptr() if diag is not None else None, _stream(stream)))
+
+
+def ke_seed(prm, dp, scale: float, lam, stream=None):
+    """sph_ke_seed: lam = adjoint of scale * KE at dp's state."""
+    s = dp.struct(prm)
+    _rc(lib().sph_ke_seed(ctypes.byref(prm), ctypes.byref(s), float(scale), lam.data_ptr(),
+                          _stream(stream)))
 
 
 def step_backward(prm, ckpt: DeviceParticles, k: int, lam_in, lam_out, dJ_dnu, ws, stream=None):

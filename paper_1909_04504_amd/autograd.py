@@ -12,8 +12,8 @@ from __future__ import annotations
 
 import torch
 
-from . import (DeviceParticles, FP64, accel_backward, make_params, step, step_backward,
-               workspace)
+from . import (DeviceParticles, FP64, accel_backward, ke_seed, make_params, step,
+               step_backward, workspace)
 
 
 class SPHRollout(torch.autograd.Function):
@@ -56,9 +56,9 @@ class SPHRollout(torch.autograd.Function):
     def backward(ctx, g):
         prm, ckpts, segs, final, ws, dim, n = ctx.state
         dev = final.u.device
-        lam = torch.zeros((3 * dim, n), dtype=torch.float64, device=dev)
-        # seed: dKE/du^N = m u^N (walls carry u = 0)
-        lam[dim:2 * dim] = g.to(torch.float64) * final.m * final.u
+        lam = torch.empty((3 * dim, n), dtype=torch.float64, device=dev)
+        # seed: dKE/du^N = g m u^N (walls carry u = 0), formed by the library
+        ke_seed(prm, final, float(g), lam)
         other = torch.empty_like(lam)
         dJ = torch.zeros(1, dtype=torch.float64, device=dev)
         for ck, kk in zip(reversed(ckpts), reversed(segs)):

@@ -187,6 +187,24 @@ int sph_step_backward(const sph_params* prm, const sph_particles* ckpt, int64_t 
     });
 }
 
+int sph_ke_seed(const sph_params* prm, const sph_particles* pa, double scale, double* lam,
+                void* stream) {
+    g_err.clear();
+    SPH_TRY(check_params(prm, false));
+    SPH_TRY(check_particles(prm, pa));
+    if (!lam) return fail(SPH_EINVAL, "lam is NULL");
+    if (!std::isfinite(scale)) return fail(SPH_EINVAL, "scale must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)pa->n;
+    if (prm->dim == 2)
+        launch(K_ADJ_SEED, sph::k_ke_seed<2>, blocks_for(n), st, n, (const double*)pa->u[0],
+               (const double*)pa->u[1], (const double*)nullptr, (const double*)pa->m, scale, lam);
+    else
+        launch(K_ADJ_SEED, sph::k_ke_seed<3>, blocks_for(n), st, n, (const double*)pa->u[0],
+               (const double*)pa->u[1], (const double*)pa->u[2], (const double*)pa->m, scale, lam);
+    return launch_check("k_ke_seed");
+}
+
 int sph_accel_backward(const sph_params* prm, const sph_particles* st, const double* lam_a,
                        double* lam_x, double* lam_u, double* dJ_dnu, void* ws, size_t ws_bytes,
                        void* stream) {

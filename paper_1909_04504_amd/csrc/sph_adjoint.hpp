@@ -260,6 +260,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_accum(int n, const double* __res
     }
 }
 
+// Adjoint seed of the objective J = scale * sum_i m_i |u_i|^2 / 2 at a state:
+// lam_x = 0, lam_u = scale m u (walls carry u = 0), lam_a = 0, in the
+// [lam_x | lam_u | lam_a] layout of sph_step_backward.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_ke_seed(int n, const double* __restrict__ ux,
+                                                    const double* __restrict__ uy,
+                                                    const double* __restrict__ uz,
+                                                    const double* __restrict__ m, double scale,
+                                                    double* __restrict__ lam) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t N = n;
+    const double* u[3] = {ux, uy, uz};
+    const double w = scale * m[i];
+    for (int k = 0; k < DIM; ++k) {
+        lam[k * N + i] = 0.0;
+        lam[(DIM + k) * N + i] = w * u[k][i];
+        lam[(2 * DIM + k) * N + i] = 0.0;
+    }
+}
+
 // Fixed-order FP64 sum: per-block partials, then one block adds the total
 // to *out.
 static __global__ __launch_bounds__(kBlock) void k_sum_partial(int n, const double* __restrict__ v,

@@ -1238,8 +1238,10 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
     // stencil position of lane s's segment
     const int sk = lane & 1, syi = (lane >> 1) % NR, szi = (lane >> 1) / NR;
     const int soy = syi - SR, soz = DIM == 3 ? szi - SR : 0;
-    // FP64 records far from the cell (outside the box) take the exact test
-    const float far = (float)(4.0 * (G.cs[0] + G.cs[1] + G.cs[2]));
+    // FP64 records far from the cell (outside the box) take the exact test;
+    // "far" is four cell sizes summed over the used axes (the unused z axis
+    // of a 2D grid has a placeholder size)
+    const float far = (float)(4.0 * (G.cs[0] + G.cs[1] + (DIM == 3 ? G.cs[2] : 0.0)));
     // Slot ranges of cell c (tb, te: the targets; lane s: segment s) and the
     // segments' packed stencil data (oy, oz, wx, wy, wz as 3-bit fields, the
     // code base above them) and x offset terms.  The loads of the next cell

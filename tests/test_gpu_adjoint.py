@@ -136,3 +136,45 @@ def test_accel_backward_matches_oracle_transpose():
         assert normwise(lx.cpu().numpy(), rx) < tol
         assert normwise(lu.cpu().numpy(), rv) < tol
         assert float(dJ[0]) == pytest.approx(rnu, rel=tol * 10)
+
+
+def test_adjoint_at_full_size_256_vs_central_differences():
+    """The differentiation workload at its stated size: 256x256 Taylor-Green,
+    200 mixed-precision steps, checkpoint every 20.  dKE/dnu from the adjoint
+    against a central difference of the same forward (absolute step 1e-4 on
+    nu), and the directional derivative along a unit-RMS random field w of
+    u0 against a central difference with step 1e-4; both within 1e-2."""
+    wl = W.workload("tg256")
+    p, s = wl.params, wl.state
+    nsteps, k, eps = 200, 20, 1e-4
+    ke, gu, gnu = _grads(p, s, nsteps, k, sph.FP32_MIXED)
+
+    def ke_at(nu, u):
+        prm = sph.make_params(p.replace(nu=nu), sph.FP32_MIXED)
+        dp = sph.DeviceParticles.from_state(W.State(s.x, u, s.m, s.ptype, s.pid), sph.FP32_MIXED)
+        ws = sph.workspace(prm, s.n)
+        diag = torch.zeros((nsteps, 3), dtype=torch.float64, device="cuda")
+        sph.step(prm, dp, nsteps, ws, prime=True, diag=diag)
+        return float(diag[-1, 0])
+
+    assert ke == pytest.approx(ke_at(p.nu, s.u), rel=1e-12)
+    fd_nu = (ke_at(p.nu + eps, s.u) - ke_at(p.nu - eps, s.u)) / (2 * eps)
+    assert gnu == pytest.approx(fd_nu, rel=1e-2)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal(s.u.shape)
+    w /= np.sqrt(np.mean(w * w))
+    fd_u = (ke_at(p.nu, s.u + eps * w) - ke_at(p.nu, s.u - eps * w)) / (2 * eps)
+    assert np.sum(gu * w) == pytest.approx(fd_u, rel=1e-2)
+
+
+def test_ke_seed():
+    """sph_ke_seed: lam_u = scale m u, lam_x = lam_a = 0, walls zero."""
+    for p, s in (W.taylor_green(12, jitter=0.2, seed=1), W.dam_break_3d(dx=0.1)):
+        prm = sph.make_params(p, sph.FP64)
+        dp = sph.DeviceParticles.from_state(s, sph.FP64)
+        d = p.dim
+        lam = torch.full((3 * d, s.n), np.nan, dtype=torch.float64, device="cuda")
+        sph.ke_seed(prm, dp, 0.75, lam)
+        got = lam.cpu().numpy()
+        assert np.all(got[:d] == 0) and np.all(got[2 * d:] == 0)
+        assert np.array_equal(got[d:2 * d], 0.75 * s.m * s.u)

@@ -418,3 +418,31 @@ def test_exact_ties_on_dyadic_lattice(dim, cell_div, prec):
     rho, _, a = oracle.evaluate(p, st["x"], st["u"], st["m"], st["type"])
     assert normwise(st["rho"], rho) < TOL_RHO[prec]
     assert normwise(st["a"], a) < TOL_ACC[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_clamped_particle_lists_match_walks_2d(prec):
+    """Particles outside a non-periodic 2D box are clamped into edge cells;
+    the cell-cooperative list build (whose FP32 filter hands records far from
+    the cell to the exact test) gives the fields of the cell walks, and
+    sph_check reports the particles."""
+    p, s = make_case("box2d")
+    x = s.x.copy()
+    fl = np.where(s.ptype == 0)[0]
+    R = support_radius(p)
+    x[:, fl[0]] = (p.lo[0] - 0.2 * R, p.lo[1] + 0.5)
+    x[:, fl[1]] = (p.lo[0] - 0.6 * R, p.lo[1] + 0.5 + 0.1 * R)
+    x[:, fl[2]] = (p.hi[0] + 0.3 * R, p.hi[1] + 0.2 * R)
+    s = W.State(x, s.u, s.m, s.ptype, s.pid)
+    outs = []
+    for cap in (0, -1):
+        prm = sph.make_params(p, prec, cap)
+        dp = sph.DeviceParticles.from_state(s, prec)
+        ws = sph.workspace(prm, s.n)
+        sph.step(prm, dp, 0, ws, prime=True)
+        with pytest.raises(sph.SphError) as ei:
+            sph.check(ws)
+        assert ei.value.code == sph.SPH_EDOMAIN
+        outs.append(dp.numpy())
+    for f in ("a", "rho", "p", "id"):
+        assert np.array_equal(outs[0][f], outs[1][f]), f
