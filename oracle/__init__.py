@@ -27,7 +27,7 @@ _P = ctypes.c_void_p
 
 class OrcParams(ctypes.Structure):
     _fields_ = [("dim", _i32), ("kernel", _i32), ("cell_div", _i32), ("brute", _i32),
-                ("periodic", _i32 * 3), ("pad_", _i32),
+                ("periodic", _i32 * 3), ("cell_order", _i32),
                 ("h", _d), ("rho0", _d), ("c0", _d), ("nu", _d), ("eta", _d), ("dt", _d),
                 ("g", _d * 3), ("lo", _d * 3), ("hi", _d * 3)]
 
@@ -58,6 +58,8 @@ def lib():
         L.orc_kernel_d2wdr2.restype = _d
         L.orc_kernel_d2wdr2.argtypes = [_P, _d]
         L.orc_grid.argtypes = [_P, _P, _P]
+        L.orc_nkeys.restype = _i64
+        L.orc_nkeys.argtypes = [_P]
         L.orc_cell_keys.argtypes = [_P, _i64, _P, _P]
         L.orc_bin_sort.argtypes = [_P, _i64, _P, _P, _P, _P, _P]
         L.orc_neighbors.restype = _i64
@@ -96,6 +98,7 @@ def params(p, brute: bool = False) -> OrcParams:
     o.dim = p.dim
     o.kernel = p.kernel
     o.cell_div = p.cell_div
+    o.cell_order = int(getattr(p, "cell_order", 0))
     o.brute = 1 if brute else 0
     for k in range(3):
         o.periodic[k] = int(p.periodic[k])
@@ -155,8 +158,8 @@ def bin_sort(p, x):
     """(keys_sorted, perm, cell_start, cell_end) of a stable sort by cell key."""
     x = _c(x, np.float64)
     n = x.shape[1]
-    nc, _ = grid(p)
-    ncells = int(np.prod(nc[:p.dim]))
+    ncells = int(lib().orc_nkeys(ctypes.byref(params(p))))
+    _check(0 if ncells > 0 else -1)
     keys = np.zeros(n, np.uint32)
     perm = np.zeros(n, np.int64)
     cs = np.zeros(ncells, np.uint32)

@@ -45,7 +45,7 @@ struct OrcParams {
     int32_t cell_div;    /* cells per support radius along an axis (>= 1) */
     int32_t brute;       /* 1: brute-force neighbour sets; 0: cell list */
     int32_t periodic[3];
-    int32_t pad_;
+    int32_t cell_order;  /* sort key: 0 = row-major, 1 = Z-order (Morton) of the cell coordinates */
     double h;            /* smoothing length; support radius R = 2h, 3h for the quintic (A1) */
     double rho0;         /* reference density */
     double c0;           /* reference speed of sound */
@@ -172,6 +172,8 @@ struct Grid {
     double cs[3];
     int64_t ncells;
     int stencil;  /* cells searched on each side of the home cell */
+    int64_t nkeys;  /* size of the sort-key space: ncells (row-major) or 2^(dim bits) (Z-order) */
+    int bits;       /* Z-order: bits per coordinate, the smallest with 2^bits >= every nc */
 };
 
 /* Cells of size >= R / cell_div on every axis; returns false if a periodic
@@ -195,6 +197,16 @@ bool make_grid(const OrcParams& P, Grid& G) {
         G.ncells *= nc;
         if (G.ncells > (int64_t)1 << 31) return false; /* keys are 31-bit */
     }
+    G.nkeys = G.ncells;
+    G.bits = 0;
+    if (P.cell_order == 1) {
+        int64_t m = 1;
+        for (int k = 0; k < P.dim; ++k) m = std::max(m, G.nc[k]);
+        while (((int64_t)1 << G.bits) < m) ++G.bits;
+        if (G.bits < 1) G.bits = 1;
+        if (P.dim * G.bits > 31) return false;
+        G.nkeys = (int64_t)1 << (P.dim * G.bits);
+    }
     return true;
 }
 
@@ -211,6 +223,20 @@ uint32_t cell_key(const OrcParams& P, const Grid& G, int64_t n, const double* x,
     int64_t c[3] = {0, 0, 0};
     for (int k = 0; k < P.dim; ++k) c[k] = cell_coord(P, G, x[k * n + i], k);
     return (uint32_t)(c[0] + G.nc[0] * (c[1] + G.nc[1] * c[2]));
+}
+
+/* Sort key of the cell of particle i (Section 2.2 sorts by a cell key; the
+ * paper's GPU search uses Z-order keys): row-major as cell_key, or the
+ * Z-order (Morton) key, whose bit 3b + k (3D; dim b + k in general) is bit
+ * b of the cell coordinate along axis k. */
+uint32_t sort_key(const OrcParams& P, const Grid& G, int64_t n, const double* x, int64_t i) {
+    if (P.cell_order != 1) return cell_key(P, G, n, x, i);
+    int64_t c[3] = {0, 0, 0};
+    for (int k = 0; k < P.dim; ++k) c[k] = cell_coord(P, G, x[k * n + i], k);
+    uint64_t key = 0;
+    for (int b = 0; b < G.bits; ++b)
+        for (int k = 0; k < P.dim; ++k) key |= (uint64_t)((c[k] >> b) & 1) << (P.dim * b + k);
+    return (uint32_t)key;
 }
 
 /* Neighbour lists as CSR: nbr[off[i] .. off[i+1]) ascending j. */
@@ -569,24 +595,32 @@ int orc_grid(const OrcParams* P, int64_t* nc, double* cs) {
     return 0;
 }
 
+/* Size of the sort-key space (cells, or Z-order keys). */
+int64_t orc_nkeys(const OrcParams* P) {
+    Grid G;
+    if (!make_grid(*P, G)) return -1;
+    return G.nkeys;
+}
+
 /* Cell keys of every particle (A14, A15). */
 int orc_cell_keys(const OrcParams* P, int64_t n, const double* x, uint32_t* keys) {
     Grid G;
     if (!make_grid(*P, G)) return -1;
-    for (int64_t i = 0; i < n; ++i) keys[i] = cell_key(*P, G, n, x, i);
+    for (int64_t i = 0; i < n; ++i) keys[i] = sort_key(*P, G, n, x, i);
     return 0;
 }
 
-/* Stable sort of particles by cell key (Z-order style sort of the paper's
- * NNPS with a row-major key): perm[s] = index before sorting of the particle
- * in sorted slot s; keys_sorted[s] its key; cell_start/cell_end per cell
- * (empty cells: start = end = first slot of a larger key). */
+/* Stable sort of particles by sort key (row-major or Z-order cell key):
+ * perm[s] = index before sorting of the particle in sorted slot s;
+ * keys_sorted[s] its key; cell_start/cell_end per key of the key space
+ * (empty cells and unused Z-order keys: start = end = first slot of a larger
+ * key). */
 int orc_bin_sort(const OrcParams* P, int64_t n, const double* x, uint32_t* keys_sorted,
                  int64_t* perm, uint32_t* cell_start, uint32_t* cell_end) {
     Grid G;
     if (!make_grid(*P, G)) return -1;
     std::vector<uint32_t> key(n);
-    for (int64_t i = 0; i < n; ++i) key[i] = cell_key(*P, G, n, x, i);
+    for (int64_t i = 0; i < n; ++i) key[i] = sort_key(*P, G, n, x, i);
     std::vector<int64_t> order(n);
     for (int64_t i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -595,7 +629,7 @@ int orc_bin_sort(const OrcParams* P, int64_t n, const double* x, uint32_t* keys_
         perm[s] = order[s];
         keys_sorted[s] = key[order[s]];
     }
-    for (int64_t c = 0; c < G.ncells; ++c) {
+    for (int64_t c = 0; c < G.nkeys; ++c) {
         cell_start[c] = (uint32_t)(std::lower_bound(keys_sorted, keys_sorted + n, (uint32_t)c) - keys_sorted);
         cell_end[c] = (uint32_t)(std::upper_bound(keys_sorted, keys_sorted + n, (uint32_t)c) - keys_sorted);
     }

@@ -45,6 +45,8 @@ SUMMATION = 0
 CONTINUITY = 1
 PREDICTOR_CORRECTOR = 0
 EULER = 1
+# Cell sort keys: row-major (x fastest) or Z-order (Morton).
+ROW_MAJOR, Z_ORDER = 0, 1
 
 
 @dataclasses.dataclass
@@ -62,6 +64,7 @@ class Params:
     hi: Tuple[float, float, float]
     periodic: Tuple[int, int, int]
     cell_div: int = 1      # cells per support radius along an axis
+    cell_order: int = 0    # sort key: ROW_MAJOR or Z_ORDER (Morton) cell keys
     scheme: int = SUMMATION
     integrator: int = PREDICTOR_CORRECTOR
 

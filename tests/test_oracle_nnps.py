@@ -166,3 +166,66 @@ def test_cell_size_at_least_support():
         nc, cs = oracle.grid(p)
         assert np.all(cs[:3] * cd >= 2 * p.h * (1 - 1e-15))
         assert np.all(nc[:3] == np.floor(1.0 * cd / (2 * p.h)))
+
+
+def _cell_centres(p, cells):
+    """Positions at the centres of the given cells (dim x m integer array)."""
+    nc, cs = oracle.grid(p)
+    return np.array([p.lo[k] + (cells[k] + 0.5) * cs[k] for k in range(p.dim)], np.float64)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_z_order_key_recursion(dim):
+    """Z-order (Morton) keys follow the curve's recursive definition: the
+    cell (2x + a, 2y + b[, 2z + c]) of a grid of 2^k cells per axis has key
+    2^dim key(x, y[, z]) + a + 2b[ + 4c] -- the 2^dim children of a cell in
+    order x fastest, then y, then z -- and key(0) = 0.  Checked over every
+    cell of a 16^dim grid (so the whole bit interleave is pinned)."""
+    n = 16
+    p = W.Params(dim=dim, kernel=W.CUBIC, h=0.5 / n, rho0=1.0, c0=10.0, nu=0.01, eta=0.01,
+                 dt=1e-4, g=(0, 0, 0), lo=(0, 0, 0), hi=(1, 1, 1 if dim == 3 else 0),
+                 periodic=(1, 1, 1 if dim == 3 else 0), cell_order=W.Z_ORDER)
+    nc, _ = oracle.grid(p)
+    assert np.all(nc[:dim] == n)
+    cells = np.array(np.meshgrid(*[np.arange(n)] * dim, indexing="ij")).reshape(dim, -1)
+    keys = oracle.cell_keys(p, _cell_centres(p, cells)).astype(np.int64)
+    key = {tuple(c): k for c, k in zip(cells.T.tolist(), keys.tolist())}
+    assert key[(0,) * dim] == 0
+    assert sorted(keys.tolist()) == list(range(n ** dim))   # a bijection onto [0, n^dim)
+    for c, k in key.items():
+        parent = tuple(v // 2 for v in c)
+        child = sum((v % 2) << a for a, v in enumerate(c))
+        assert k == (key[parent] << dim) + child, (c, k)
+
+
+def test_z_order_pads_to_a_power_of_two_grid():
+    """With nc = 5 cells per axis the keys live in the 8^3 key space of the
+    smallest power-of-two grid: cell (4, 4, 4) is the first child of the
+    first child of the last octant, key 7 * 64; the sort's cell ranges cover
+    the whole key space."""
+    p, x = _jittered(3, 10, 0.2, seed=3)
+    p = p.replace(h=0.1, cell_order=W.Z_ORDER)   # R = 0.2: 5 cells per axis
+    nc, _ = oracle.grid(p)
+    assert np.all(nc[:3] == 5)
+    k = oracle.cell_keys(p, _cell_centres(p, np.array([[4], [4], [4]])))
+    assert int(k[0]) == 7 * 64
+    ks, perm, cs, ce = oracle.bin_sort(p, x)
+    assert len(cs) == 8 ** 3
+    assert int((ce.astype(np.int64) - cs).sum()) == x.shape[1]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_z_order_bin_sort_is_numpy_stable_sort(dim):
+    p, x = _jittered(dim, 18 if dim == 2 else 9, 0.45, seed=12)
+    p = p.replace(cell_order=W.Z_ORDER)
+    keys = oracle.cell_keys(p, x)
+    ks, perm, cs, ce = oracle.bin_sort(p, x)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(perm, order)
+    assert np.array_equal(ks, keys[order])
+    for s in range(x.shape[1]):
+        assert cs[ks[s]] <= s < ce[ks[s]]
+    # the order of the sort keys does not change the neighbour sets
+    off_r, idx_r = oracle.neighbors(p.replace(cell_order=W.ROW_MAJOR), x)
+    off_z, idx_z = oracle.neighbors(p, x)
+    assert np.array_equal(off_r, off_z) and np.array_equal(idx_r, idx_z)
