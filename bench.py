@@ -132,9 +132,9 @@ def traffic_from_profile(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def run_precision(sph, torch, wl, prec, steps, warmup, timing, nbr_cap=0):
+def run_precision(sph, torch, wl, prec, steps, warmup, timing, nbr_cap=0, pair_tiles=0):
     p, s = wl.params, wl.state
-    prm = sph.make_params(p, prec, nbr_cap)
+    prm = sph.make_params(p, prec, nbr_cap, pair_tiles)
     dp = sph.DeviceParticles.from_state(s, prec, scheme=p.scheme)
     ws = sph.workspace(prm, s.n)
     sph.step(prm, dp, 0, ws, prime=True)
@@ -486,9 +486,14 @@ def main():
     ap.add_argument("--workload", default="cube256")
     ap.add_argument("--cell-div", type=int, default=0,
                     help="cells per support radius (default: the workload's)")
+    ap.add_argument("--cell-order", choices=("row", "z"), default="row",
+                    help="sort key of the cells: row-major or Z-order (3D)")
     ap.add_argument("--nbr-cap", type=int, default=0,
                     help="neighbour-list capacity per particle (0: the library default, "
                          "-1: no lists, every pair pass walks the cells)")
+    ap.add_argument("--pair-tiles", type=int, default=0,
+                    help="LDS-tiled 3D mixed-precision passes: 0 where they apply, -1 never, "
+                         "k > 0 at most k staged particles per tile")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -528,9 +533,11 @@ def main():
     wl = W.workload(args.workload)
     if args.cell_div:
         wl.params = wl.params.replace(cell_div=args.cell_div)
+    if args.cell_order == "z":
+        wl.params = wl.params.replace(cell_order=W.Z_ORDER)
     note(f"# workload {wl.name}: {wl.description}; n={wl.state.n}")
     mixed = run_precision(sph, torch, wl, sph.FP32_MIXED, args.steps, args.warmup, True,
-                          args.nbr_cap)
+                          args.nbr_cap, args.pair_tiles)
     note(f"# fp32-mixed: {mixed['ms_per_step']:.4f} ms/step")
     fp64 = None
     if not args.no_fp64:
@@ -585,8 +592,10 @@ def main():
         "config": {"workload": wl.name, "description": wl.description, "particles": wl.state.n,
                    "kernel": KERNEL_NAMES[wl.params.kernel], "h": wl.params.h,
                    "scheme": ("continuity" if wl.params.scheme == 1 else "summation"),
-                   "cell_div": wl.params.cell_div, "rebuild": "every step",
-                   "nbr_cap": args.nbr_cap},
+                   "cell_div": wl.params.cell_div,
+                   "cell_order": "z-order" if wl.params.cell_order else "row-major",
+                   "rebuild": "every step",
+                   "nbr_cap": args.nbr_cap, "pair_tiles": args.pair_tiles},
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": rl,
         "fp32_mixed": mixed,

@@ -113,11 +113,20 @@ typedef struct {
     int32_t pair_tiles;   /* 3D mixed-precision summation passes (Section
                            * 2.2's cell grid cut into boxes whose particles
                            * and neighbour cells are staged in on-chip
-                           * memory): 0 = used where they apply (default),
-                           * < 0 = never (lists read from global memory),
-                           * k > 0 = used with at most k staged particles per
-                           * box (larger boxes take the cell walk).  Results do
-                           * not depend on it. */
+                           * memory): 0 = used where they apply on grids with
+                           * at least one particle per cell on average
+                           * (default), < 0 = never (lists read from global
+                           * memory), k > 0 = used wherever they apply, with at
+                           * most k staged particles per box (3072 at most;
+                           * larger boxes take the cell walk).  Results do not
+                           * depend on it. */
+    int32_t cell_order;   /* sort key of the cells (Section 2.2): 0 = row-major,
+                           * x fastest (default); 1 = Z-order (Morton, the
+                           * bits of the three cell coordinates interleaved,
+                           * x lowest), 3D only.  Z-order keys span the smallest
+                           * power-of-two grid holding every axis, so
+                           * sph_grid's ncells (the length of cell_start and
+                           * cell_end) is 8^bits. */
 } sph_params;
 
 /* Particle arrays (device pointers, caller-owned). */
@@ -151,7 +160,7 @@ size_t sph_workspace_bytes(const sph_params* prm, int64_t n, int64_t adjoint_k);
 /* Neighbour-search build (Section 2.2; the Z-order-style build sorts particle
  * ids by a cell key): hash every particle to its cell
  *   c_k = clamp(floor((x_k - lo_k) / cs_k), 0, nc_k - 1),
- *   key = c_0 + nc_0 (c_1 + nc_1 c_2),
+ *   key = c_0 + nc_0 (c_1 + nc_1 c_2)   (or the Z-order key, prm->cell_order),
  * sort the particles stably by key (ties keep their current order), permute
  * every particle array in place into that order, and write per cell the slot
  * range [cell_start[c], cell_end[c]) of its particles (empty cells:

@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
                 ("periodic", _i32 * 3), ("nbr_cap", _i32),
                 ("h", _d), ("rho0", _d), ("c0", _d), ("nu", _d), ("eta", _d), ("dt", _d),
                 ("g", _d * 3), ("lo", _d * 3), ("hi", _d * 3),
-                ("scheme", _i32), ("integrator", _i32), ("pair_tiles", _i32)]
+                ("scheme", _i32), ("integrator", _i32), ("pair_tiles", _i32),
+                ("cell_order", _i32)]
 
 
 class Particles(ctypes.Structure):
@@ -106,6 +107,7 @@ def make_params(p, precision: int = FP64, nbr_cap: int = 0, pair_tiles: int = 0)
     c.nbr_cap = int(nbr_cap)
     c.pair_tiles = int(pair_tiles)
     c.scheme = int(getattr(p, "scheme", 0))
+    c.cell_order = int(getattr(p, "cell_order", 0))
     c.integrator = int(getattr(p, "integrator", 0))
     c.h, c.rho0, c.c0, c.nu, c.eta, c.dt = p.h, p.rho0, p.c0, p.nu, p.eta, p.dt
     return c

@@ -60,7 +60,32 @@ struct Grid {
     // and shift (Granlund and Montgomery, 1994): magic, shift 1, shift 2
     uint32_t dmag[2];
     int dsh1[2], dsh2[2];
+    // sort key: 0 = row-major (x fastest), 1 = Z-order (Morton, 3D only):
+    // bit 3b + k of the key is bit b of the cell coordinate along axis k,
+    // over mbits bits per coordinate (keys in [0, 8^mbits))
+    int order;
+    int mbits;
 };
+
+// Bits 0..9 of v moved to bits 0, 3, 6, ..., 27 (and back): the bit
+// interleave of the Z-order key by masked shifts, four steps of halving
+// strides (16, 8, 4, 2) instead of a loop over bits.
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
 
 // Magic numbers of unsigned 32-bit division by d >= 1 (round-up method with
 // the add step): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1 (mod
@@ -329,7 +354,20 @@ __device__ __forceinline__ uint32_t div_by(uint32_t n, const Grid& G, int a) {
     const uint32_t t = __umulhi(G.dmag[a], n);
     return (t + ((n - t) >> G.dsh1[a])) >> G.dsh2[a];
 }
+// Sort key of cell c (row-major or Z-order).
+__device__ __forceinline__ uint32_t cell_key(const int c[3], const Grid& G) {
+    if (G.order)
+        return spread3((uint32_t)c[0]) | (spread3((uint32_t)c[1]) << 1) |
+               (spread3((uint32_t)c[2]) << 2);
+    return (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
+}
 __device__ __forceinline__ void decode_key(uint32_t key, const Grid& G, int c[3]) {
+    if (G.order) {
+        c[0] = (int)compact3(key);
+        c[1] = (int)compact3(key >> 1);
+        c[2] = (int)compact3(key >> 2);
+        return;
+    }
     const uint32_t q = div_by(key, G, 0);
     c[0] = (int)(key - q * (uint32_t)G.nc[0]);
     const uint32_t r = div_by(q, G, 1);
@@ -604,6 +642,41 @@ __device__ __forceinline__ void walk_pairs(const Grid& G, const PairConst<T>& C,
     constexpr int NR = 2 * S + 1;
     int c[3];
     decode_key(key, G, c);
+    if (DIM == 3 && G.order) {
+        // Z-order keys: the cells of a stencil row are not adjacent in
+        // memory, so each cell is a slot range of its own; same cell order
+        // (rows in stencil order, x ascending) and the same codes
+#pragma unroll 1
+        for (int zi = 0; zi < NR; ++zi) {
+            const int oz = zi - S;
+            int cz, wz;
+            if (!stencil_axis(c[2], oz, G.nc[2], G.periodic[2], &cz, &wz)) continue;
+#pragma unroll 1
+            for (int yi = 0; yi < NR; ++yi) {
+                const int oy = yi - S;
+                int cy, wy;
+                if (!stencil_axis(c[1], oy, G.nc[1], G.periodic[1], &cy, &wy)) continue;
+#pragma unroll 1
+                for (int xi = 0; xi < NR; ++xi) {
+                    const int ox = xi - S;
+                    int cx, wx;
+                    if (!stencil_axis(c[0], ox, G.nc[0], G.periodic[0], &cx, &wx)) continue;
+                    const int cc[3] = {cx, cy, cz};
+                    const uint32_t ck = cell_key(cc, G);
+                    uint32_t e = cend[ck];
+                    e = e < n ? e : n;
+                    const int cb = Code::row_base(oy, oz, wx, wy, wz);
+                    for (uint32_t j = cstart[ck]; j < e; ++j) {
+                        const R rj = pos[j];
+                        const auto pj = load(j);
+                        const Geom<T> g = pair_geom<DIM>(ri, rj, ox, oy, oz, wx, wy, wz, C);
+                        if (pair_accept(g, C)) f(j, rj, pj, g, Code::code(cb, ox));
+                    }
+                }
+            }
+        }
+        return;
+    }
     int first[2], last[2], wrap[2];
     row_pieces<S>(c[0], G, first, last, wrap);
 #pragma unroll
@@ -823,7 +896,7 @@ __device__ __forceinline__ void drift_and_hash(int i, const State& S, const Grid
     if (outside) atomicOr(flags, kFlagOutside);
     if (nonfinite) atomicOr(flags, kFlagNonFinite);
     if (!hash) return;
-    const uint32_t kk = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
+    const uint32_t kk = cell_key(c, G);
     key[i] = kk;
     int leader = 0, rank = 0, size = 1;
     wave_group(kk, &leader, &rank, &size);
@@ -1056,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
         xs[q] = x;
         vv[q] = (T)S.u[q][i];
     }
-    skey[i] = (uint32_t)c[0] + (uint32_t)G.nc[0] * ((uint32_t)c[1] + (uint32_t)G.nc[1] * (uint32_t)c[2]);
+    skey[i] = cell_key(c, G);
     typename Vec4<T>::type vr;
     vr.x = vv[0]; vr.y = vv[1]; vr.z = vv[2]; vr.w = T(0);
     pos[i] = make_rec<T>(xs, c, S.m[i], (int)S.type[i], G, DIM);

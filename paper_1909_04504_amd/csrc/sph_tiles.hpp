@@ -40,7 +40,7 @@ namespace sph {
 
 constexpr int kTileThreads = 512;                // 8 waves per workgroup
 constexpr int kTileCellsMax = 1024;              // union cells per tile (two per thread)
-constexpr int kTileRowsMax = 64;                 // rows of target cells per tile
+constexpr int kTileTargetCellsMax = 128;         // target cells per tile
 constexpr int kTileCap = 3072;                   // union particles staged in LDS
 constexpr int kTileUnionAxisMax = 12;            // union cells per axis: 12 * 2^27 + 2^29 < 2^31
 constexpr uint32_t kTileOverflow = 0xffffffffu;  // count of a target left to the fallback
@@ -65,10 +65,9 @@ struct Tiles {
 struct TileMeta {
     uint32_t off[kTileCellsMax + 1];  // union index of each cell's first particle; off[ncu] = total
     uint32_t gs[kTileCellsMax];       // global slot of each cell's first particle
-    uint32_t tpre[kTileRowsMax + 1];  // targets before each target row
-    uint32_t tg[kTileRowsMax];        // global slot of each target row's first particle
-    int tc[kTileRowsMax];             // union cell of each target row's first cell
-    int ntrows, twc;
+    uint32_t tpre[kTileTargetCellsMax + 1];  // targets before each target cell
+    int tc[kTileTargetCellsMax];             // union index of each target cell
+    int ntcells;
     uint32_t total, ntargets;
     uint32_t wsum[kTileThreads / 64];
     uint16_t cellof[kTileCap];        // union cell of each staged particle
@@ -94,6 +93,7 @@ __device__ __forceinline__ uint32_t tile_scan2(uint32_t a, uint32_t b, TileMeta&
         before += k < w ? M.wsum[k] : 0u;
         all += M.wsum[k];
     }
+    __syncthreads();  // wsum is reused by the next scan
     *total = all;
     return before + incl - v;
 }
@@ -116,7 +116,26 @@ __device__ __forceinline__ void tile_origin(const Tiles& TL, int t, int c0[3]) {
     c0[2] = (t / (TL.nt[0] * TL.nt[1])) * TL.td;
 }
 
-// Cell ranges of the union, their scan, and the target rows.  Returns the
+// Whether the tile's box holds no particle: the keys of its cells lie
+// between those of its first and last corner cells (row-major and Z-order
+// keys both grow with each coordinate), so an empty slot range between them
+// means empty cells.  Two loads per workgroup, before any other work.
+__device__ __forceinline__ bool tile_empty(const Grid& G, const Tiles& TL, const int c0[3],
+                                           const uint32_t* __restrict__ cstart,
+                                           const uint32_t* __restrict__ cend) {
+    __shared__ uint32_t se[2];
+    if (threadIdx.x == 0) {
+        const int a[3] = {c0[0], c0[1], c0[2]};
+        const int b[3] = {min(c0[0] + TL.tw, G.nc[0]) - 1, min(c0[1] + TL.th, G.nc[1]) - 1,
+                          min(c0[2] + TL.td, G.nc[2]) - 1};
+        se[0] = cstart[cell_key(a, G)];
+        se[1] = cend[cell_key(b, G)];
+    }
+    __syncthreads();
+    return se[1] <= se[0];
+}
+
+// Cell ranges of the union, their scan, and the target cells.  Returns the
 // number of union particles (every thread).
 __device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, const int c0[3],
                                                const uint32_t* __restrict__ cstart,
@@ -135,7 +154,8 @@ __device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, c
             const int gz = tile_axis(G, 2, c0[2], uz, TL.S);
             uint32_t s = 0;
             if (gx >= 0 && gy >= 0 && gz >= 0) {
-                const uint32_t key = (uint32_t)gx + (uint32_t)G.nc[0] * ((uint32_t)gy + (uint32_t)G.nc[1] * (uint32_t)gz);
+                const int gc[3] = {gx, gy, gz};
+                const uint32_t key = cell_key(gc, G);
                 s = cstart[key];
                 uint32_t e = cend[key];
                 e = e < (uint32_t)n ? e : (uint32_t)n;
@@ -156,26 +176,31 @@ __device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, c
         M.total = total;
     }
     __syncthreads();
+    // target cells: the box's cells inside the grid, each its own slot range
+    // (with Z-order keys the cells of a row are not adjacent); thread r
+    // takes target cell r, and a workgroup scan gives their offsets
+    const int twc = min(TL.tw, G.nc[0] - c0[0]);
+    const int thc = min(TL.th, G.nc[1] - c0[1]);
+    const int tdc = min(TL.td, G.nc[2] - c0[2]);
+    const int ntc = twc * thc * tdc;
+    const int r = (int)threadIdx.x;
+    uint32_t tcnt = 0;
+    int tcell = 0;
+    if (r < ntc) {
+        const int x = r % twc, y = (r / twc) % thc, z = r / (twc * thc);
+        tcell = (TL.S + x) + TL.uw * ((TL.S + y) + TL.uh * (TL.S + z));
+        tcnt = M.off[tcell + 1] - M.off[tcell];
+    }
+    uint32_t ntargets;
+    const uint32_t tpre = tile_scan2(tcnt, 0u, M, &ntargets);
+    if (r < ntc) {
+        M.tc[r] = tcell;
+        M.tpre[r] = tpre;
+    }
     if (threadIdx.x == 0) {
-        // target rows: cells [S, S + twc) of union rows (S + y, S + z)
-        const int twc = min(TL.tw, G.nc[0] - c0[0]);
-        const int thc = min(TL.th, G.nc[1] - c0[1]);
-        const int tdc = min(TL.td, G.nc[2] - c0[2]);
-        int r = 0;
-        uint32_t acc = 0;
-        for (int z = 0; z < tdc; ++z)
-            for (int y = 0; y < thc; ++y) {
-                const int c = TL.S + TL.uw * ((TL.S + y) + TL.uh * (TL.S + z));
-                M.tc[r] = c;
-                M.tg[r] = M.gs[c];
-                M.tpre[r] = acc;
-                acc += M.off[c + twc] - M.off[c];
-                ++r;
-            }
-        M.tpre[r] = acc;
-        M.ntrows = r;
-        M.twc = twc;
-        M.ntargets = acc;
+        M.tpre[ntc] = ntargets;
+        M.ntcells = ntc;
+        M.ntargets = ntargets;
     }
     __syncthreads();
     return total;
@@ -184,24 +209,27 @@ __device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, c
 // Target t of the tile: its union index, global slot and union cell coords.
 __device__ __forceinline__ void tile_target(const Tiles& TL, const TileMeta& M, uint32_t t,
                                             uint32_t* ui, uint32_t* gi, int uc[3]) {
-    int r = 0;
-    while (r + 1 < M.ntrows && M.tpre[r + 1] <= t) ++r;
-    const int c = M.tc[r];
-    const uint32_t k = t - M.tpre[r];
+    // the target cell: the last r with tpre[r] <= t (binary search)
+    int lo = 0, hi = M.ntcells;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (M.tpre[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int c = M.tc[lo];
+    const uint32_t k = t - M.tpre[lo];
     *ui = M.off[c] + k;
-    *gi = M.tg[r] + k;
-    int x = 0;
-    while (x + 1 < M.twc && M.off[c + x + 1] <= *ui) ++x;
-    uc[0] = TL.S + x;
+    *gi = M.gs[c] + k;
+    uc[0] = c % TL.uw;
     uc[1] = (c / TL.uw) % TL.uh;
     uc[2] = c / (TL.uw * TL.uh);
 }
 
 // Marks every target of the tile for the fallback (its union does not fit).
 __device__ __forceinline__ void tile_mark_overflow(const TileMeta& M, uint32_t* __restrict__ ncnt) {
-    for (int r = 0; r < M.ntrows; ++r) {
+    for (int r = 0; r < M.ntcells; ++r) {
         const uint32_t len = M.tpre[r + 1] - M.tpre[r];
-        for (uint32_t k = threadIdx.x; k < len; k += kTileThreads) ncnt[M.tg[r] + k] = kTileOverflow;
+        for (uint32_t k = threadIdx.x; k < len; k += kTileThreads)
+            ncnt[M.gs[M.tc[r]] + k] = kTileOverflow;
     }
 }
 
@@ -352,6 +380,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
+    if (tile_empty(G, TL, c0, cstart, cend)) {
+        if (count_pairs) tile_count(0u, pairs, blk);
+        return;
+    }
     const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
     if (total > (uint32_t)cap_union) {
         tile_mark_overflow(M, ncnt);
@@ -486,6 +518,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_density(
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
+    if (tile_empty(G, TL, c0, cstart, cend)) return;
     const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
     if (total > (uint32_t)cap_union) return;  // every target is the fallback's
     tile_stage(TL, M, [&](uint32_t j) { return pos[j]; },
@@ -530,8 +563,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
-    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
     double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+    if (tile_empty(G, TL, c0, cstart, cend)) {
+        if (diag_part) tile_block_sum<4>(dsum, diag_part, blk, stride);
+        return;
+    }
+    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
     const bool fits = total <= (uint32_t)cap_union;
     if (fits) {
         struct Rc {

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # 8 int32 + 6 double + 9 double + 3 int32 (scheme, integrator, pair_tiles) + padding
+    # 8 int32 + 6 double + 9 double + 4 int32 (scheme, integrator, pair_tiles, cell_order)
     assert ctypes.sizeof(sph.Params) == 8 * 4 + 15 * 8 + 4 * 4
     # n, x/u/a (3 pointers each), rho, p, m, type, id, arho
     assert ctypes.sizeof(sph.Particles) == 8 + 9 * 8 + 6 * 8
@@ -81,7 +81,8 @@ def test_workspace_holds_the_neighbour_lists():
                                          ("rho0", 0.0), ("c0", 0.0), ("nu", -1.0),
                                          ("eta", -0.5), ("nbr_cap", 5000),
                                          ("scheme", 2), ("scheme", -1), ("integrator", 2),
-                                         ("integrator", 1)])
+                                         ("integrator", 1), ("cell_order", 2),
+                                         ("cell_order", -1)])
 def test_invalid_params_rejected(field, value):
     prm = _params()
     setattr(prm, field, value)

@@ -19,6 +19,7 @@ from helpers import NEAR_TIE, drop_near_ties, normwise, order_by_id, shuffled
 pytestmark = pytest.mark.gpu
 
 MIXED = sph.FP32_MIXED
+ON = 3072          # pair_tiles: tiles wherever they apply, full staging capacity
 FIELDS = ("x", "u", "a", "rho", "p", "id")
 
 
@@ -44,6 +45,7 @@ CASES = ["cube_cd1", "cube_cd2", "cube32_cd2", "quintic_cd1", "dam_cd1", "dam_cd
 
 
 def run_steps(p, s, tiles, nsteps, cap=0):
+    """tiles: sph_params.pair_tiles."""
     prm = sph.make_params(p, MIXED, cap, pair_tiles=tiles)
     dp = sph.DeviceParticles.from_state(s, MIXED)
     ws = sph.workspace(prm, s.n)
@@ -62,12 +64,12 @@ def assert_same(a, b):
 
 @pytest.mark.parametrize("name", CASES)
 def test_tiles_bitwise_equal_to_global_lists(name):
-    """Three steps with tiles (default), without (global lists) and with a
+    """Three steps with tiles (forced on), without (global lists) and with a
     staging capacity below every union (all targets on the fallback)."""
     p, s = case(name)
     s = shuffled(s, 3)
     ref, inter_ref, diag_ref = run_steps(p, s, -1, 3)
-    for tiles in (0, 64):
+    for tiles in (ON, 64):
         out, inter, diag = run_steps(p, s, tiles, 3)
         assert_same(out, ref)
         assert inter == inter_ref
@@ -85,7 +87,7 @@ def test_tiles_partial_overflow_and_list_capacity(name):
     ro, _ = oracle.neighbors(p, s.x, brute=False)
     cnt = np.diff(ro)
     split = int(np.median(cnt)) & ~7
-    for tiles, cap in ((900, 0), (0, split), (900, split)):
+    for tiles, cap in ((900, 0), (ON, split), (900, split)):
         out, inter, _ = run_steps(p, s, tiles, 2, cap)
         assert_same(out, ref)
         assert inter == inter_ref
@@ -98,7 +100,7 @@ def test_tiled_standalone_calls(name):
     p, s = case(name)
     s = drop_near_ties(p, s, NEAR_TIE[MIXED])
     outs = []
-    for tiles in (-1, 0):
+    for tiles in (-1, ON):
         prm = sph.make_params(p, MIXED, 0, pair_tiles=tiles)
         dp = sph.DeviceParticles.from_state(shuffled(s, 4), MIXED)
         ws = sph.workspace(prm, s.n)
@@ -129,7 +131,7 @@ def test_tiles_with_particle_outside_box():
     x[:, fl[1]] = (p.lo[0] - 0.9 * p.h, x[1, fl[0]] + 0.2 * p.h, x[2, fl[0]])
     s = W.State(x, s.u, s.m, s.ptype, s.pid)
     outs = []
-    for tiles in (-1, 0):
+    for tiles in (-1, ON):
         prm = sph.make_params(p, MIXED, 0, pair_tiles=tiles)
         dp = sph.DeviceParticles.from_state(s, MIXED)
         ws = sph.workspace(prm, s.n)
@@ -149,7 +151,7 @@ def test_tiled_rollout_gradient_equal():
     from paper_1909_04504_amd.autograd import rollout_ke
     p, s = case("cube_cd2")
     res = []
-    for tiles in (-1, 0):
+    for tiles in (-1, ON):
         pp = p
         u0 = torch.tensor(s.u, dtype=torch.float64, device="cuda", requires_grad=True)
         nu = torch.tensor(pp.nu, dtype=torch.float64, requires_grad=True)
@@ -183,3 +185,22 @@ def test_cube_full_size_tiles_sampled():
     rho, _, a = oracle.eval_subset(p, s.x, s.u, s.m, s.ptype, sub)
     assert normwise(rho_g, rho) < 1e-5
     assert normwise(a_g, a) < 1e-4
+
+
+def test_default_uses_tiles_on_dense_grids_only():
+    """pair_tiles = 0 takes the tiles on a grid with at least one particle
+    per cell on average (the periodic cube) and the global lists on a
+    sparser one (the dam break's tank)."""
+    for name, tiled in (("cube_cd2", True), ("dam_cd2", False)):
+        p, s = case(name)
+        prm = sph.make_params(p, MIXED)
+        dp = sph.DeviceParticles.from_state(s, MIXED)
+        ws = sph.workspace(prm, s.n)
+        sph.timer_read(reset=True)
+        sph.timer_enable(True)
+        sph.step(prm, dp, 1, ws, prime=True)
+        torch.cuda.synchronize()
+        sph.timer_enable(False)
+        used = {k for k, (ms, c) in sph.timer_read(reset=True).items() if c > 0}
+        assert ("tile_build" in used) == tiled, (name, used)
+        assert ("nlist" in used) == (not tiled), (name, used)
