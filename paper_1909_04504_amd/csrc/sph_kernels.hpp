@@ -868,12 +868,13 @@ __device__ __forceinline__ void drift_and_hash(int i, const State& S, const Grid
                                                const double* u, const double* a, double hdt,
                                                double dt, bool drift, uint32_t* __restrict__ key,
                                                uint32_t* __restrict__ counts,
-                                               uint32_t* __restrict__ flags, bool hash = true) {
+                                               uint32_t* __restrict__ flags, bool hash = true,
+                                               const double* x_in = nullptr) {
 #pragma clang fp contract(off)
     bool outside = false, nonfinite = false;
     int c[3] = {0, 0, 0};
     for (int k = 0; k < DIM; ++k) {
-        double x = S.x[k][i];
+        double x = x_in ? x_in[k] : S.x[k][i];
         if (drift) {
             double v = 0.0;
             if (fluid) {
@@ -1601,8 +1602,26 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
     if (count_pairs) block_count(cnt, pairs, blk);
 }
 
+// Per-particle state that momentum_close reads (u; x when it drifts; m for
+// the diagnostics), loaded by close_load; the tile pass loads it before its
+// pair loop so that the loads' latency hides behind the loop.
+struct CloseIn {
+    double u[3], x[3], m;
+};
+template <int DIM>
+__device__ __forceinline__ CloseIn close_load(int i, const State& S, int drift, bool diag) {
+    CloseIn c;
+    for (int k = 0; k < 3; ++k) c.u[k] = c.x[k] = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+        c.u[k] = S.u[k][i];
+        if (drift) c.x[k] = S.x[k][i];
+    }
+    c.m = diag ? S.m[i] : 0.0;
+    return c;
+}
+
 // Closing epilogue of the momentum pass for slot i with acceleration acc
-// (FP64, per particle, in registers):
+// (FP64, per particle, in registers; its loads come from close_load):
 //   kick  = 1: close the step, u = v + dt/2 a (walls: u = 0);
 //   dv: m|u|^2/2 and m u after it (for the diagnostics' block sums);
 //   drift = 1: open the next step (half kick, drift, wrap, hash and count),
@@ -1613,18 +1632,18 @@ __device__ __forceinline__ void momentum_close(int i, const T acc[3], bool fluid
                                                double dt, uint32_t* __restrict__ key,
                                                uint32_t* __restrict__ counts,
                                                uint32_t* __restrict__ flags, bool diag,
-                                               double dv[1 + DIM]) {
+                                               double dv[1 + DIM], const CloseIn& ci) {
     for (int k = 0; k < DIM; ++k) ((T*)S.a[k])[i] = acc[k];
     double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
     {
 #pragma clang fp contract(off)
         for (int k = 0; k < DIM; ++k) {
             a[k] = (double)acc[k];
-            const double uk = S.u[k][i];
+            const double uk = ci.u[k];
             u[k] = kick ? (fluid ? uk + hdt * a[k] : 0.0) : uk;
         }
         if (diag) {
-            const double m = S.m[i];
+            const double m = ci.m;
             double u2 = 0.0;
             for (int k = 0; k < DIM; ++k) {
                 u2 += u[k] * u[k];
@@ -1634,7 +1653,7 @@ __device__ __forceinline__ void momentum_close(int i, const T acc[3], bool fluid
         }
     }
     if (drift) {
-        drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags);
+        drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags, true, ci.x);
     } else if (kick) {
         for (int k = 0; k < DIM; ++k) S.u[k][i] = u[k];
     }
@@ -1679,7 +1698,7 @@ __device__ __forceinline__ void momentum_one(
         acc[2] = az;
     }
     momentum_close<DIM, T>(i, acc, fluid, S, G, kick, drift, hdt, dt, key, counts, flags, diag,
-                           dv);
+                           dv, close_load<DIM>(i, S, drift, diag));
 }
 
 // Momentum equation for fluid particles (walls: a = 0), over the lists (or

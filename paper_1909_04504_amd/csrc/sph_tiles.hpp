@@ -70,7 +70,6 @@ struct TileMeta {
     int ntcells;
     uint32_t total, ntargets;
     uint32_t wsum[kTileThreads / 64];
-    uint16_t cellof[kTileCap];        // union cell of each staged particle
 };
 
 // Exclusive scan of two counts per thread (cells 2t, 2t+1) over the
@@ -237,13 +236,14 @@ __device__ __forceinline__ void tile_mark_overflow(const TileMeta& M, uint32_t* 
 // particle u held in global slot j of union cell (ux, uy, uz).  The cell of
 // every union index is noted first, so that each thread then loads four
 // particles at a time (independent loads in flight) at indices t, t + 512, ...
-// (kTileCap <= 8 * kTileThreads: a single round)
+// (kTileCap <= 8 * kTileThreads: a single round).  cellof: kTileCap entries
+// of LDS, the union cell of each staged particle (free again on return).
 template <typename Load, typename Store>
-__device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, Load&& load,
-                                           Store&& store) {
+__device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, uint16_t* cellof,
+                                           Load&& load, Store&& store) {
     const int ncu = TL.uw * TL.uh * TL.ud;
     for (int c = threadIdx.x; c < ncu; c += kTileThreads)
-        for (uint32_t u = M.off[c]; u < M.off[c + 1]; ++u) M.cellof[u] = (uint16_t)c;
+        for (uint32_t u = M.off[c]; u < M.off[c + 1]; ++u) cellof[u] = (uint16_t)c;
     __syncthreads();
     const uint32_t total = M.total;
     using P = decltype(load(0u));
@@ -255,7 +255,7 @@ __device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, Load&& 
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             const uint32_t u = b + (uint32_t)q * kTileThreads;
-            cq[q] = u < total ? (int)M.cellof[u] : 0;
+            cq[q] = u < total ? (int)cellof[u] : 0;
             if (u < total) v[q] = load(M.gs[cq[q]] + (u - M.off[cq[q]]));
         }
 #pragma unroll
@@ -288,25 +288,44 @@ __device__ __forceinline__ uint32_t half_of(const uint4& v, int e) {
     return (e & 1) ? (w >> 16) : (w & 0xffffu);
 }
 
-// Calls body(load(u)) for the cnt entries u of slot i's list, in order.
-// The loads of a full octet's eight entries are issued together and the
-// octets two ahead are fetched meanwhile; the last, partial octet goes entry
-// by entry.
+// The first two octets of slot i's list, fetched before its count is known
+// (both within the slot's cap / 8 octets, so always in bounds), for
+// tile_list_loop.
+struct ListHead {
+    uint4 o0, o1;
+};
+__device__ __forceinline__ ListHead tile_list_head(const uint4* __restrict__ list, uint32_t i,
+                                                  uint32_t cap) {
+    const uint4* __restrict__ base = list + tile_octet(i, cap, 0);
+    return ListHead{base[0], base[cap >= 16 ? 64 : 0]};
+}
+
+// Calls body(load(u)) for the cnt entries u of slot i's list, in order
+// (head: tile_list_head of the slot).  The loads of a full octet's eight
+// entries are issued together and the next octet is fetched meanwhile; the
+// last, partial octet goes entry by entry.  Octet fetches are unconditional,
+// their index clamped to the list's last octet, so that the rotating octets
+// stay in registers (a conditional fetch makes the compiler keep them in
+// scratch memory and wait on every fetch at the top of the loop).  Two
+// octets per iteration, for a longer fetch distance, measured slower (the
+// larger code and register count cost more than the latency they hide).
 template <typename Load, typename Body>
 __device__ __forceinline__ void tile_list_loop(const uint4* __restrict__ list, uint32_t i,
-                                               uint32_t cap, uint32_t cnt, Load&& load,
-                                               Body&& body) {
+                                               uint32_t cap, uint32_t cnt, const ListHead& head,
+                                               Load&& load, Body&& body) {
     using P = decltype(load(0u));
     const uint32_t nfull = cnt >> 3, rest = cnt & 7u;
     const uint32_t noct = nfull + (rest ? 1u : 0u);
     if (noct == 0) return;
-    uint4 nxt = list[tile_octet(i, cap, 0)];
-    uint4 nxt2 = nxt;
-    if (noct > 1) nxt2 = list[tile_octet(i, cap, 1)];
+    const uint32_t last = noct - 1;
+    // octet k8 of the slot is 64 k8 uint4 after its first
+    const uint4* __restrict__ base = list + tile_octet(i, cap, 0);
+    uint4 nxt = head.o0;
+    uint4 nxt2 = head.o1;
     for (uint32_t k8 = 0; k8 < nfull; ++k8) {
         const uint4 cur = nxt;
         nxt = nxt2;
-        if (k8 + 2 < noct) nxt2 = list[tile_octet(i, cap, k8 + 2)];
+        nxt2 = base[(size_t)min(k8 + 2, last) * 64];
         P p[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) p[e] = load(half_of(cur, e));
@@ -375,8 +394,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
     uint4* __restrict__ list, uint32_t* __restrict__ ncnt, int count_pairs,
     unsigned long long* __restrict__ pairs, uint32_t epoch, uint32_t* __restrict__ fallback) {
     __shared__ TileMeta M;
-    __shared__ float4 Pf[kTileCap + 8];  // + the candidates read past a row's end
-    __shared__ uint4 ring[kTileThreads][2];
+    // float copy of the union (w: the particle's union cell), + the
+    // candidates read past a row's end
+    __shared__ float4 Pf[kTileCap + 8];
+    // each thread's ring of 16 list entries (two octets), 40 bytes apart so
+    // that the lanes' appends spread over the LDS banks; the staging's cell
+    // table before that
+    constexpr int kRingStride = 5;  // uint2 per thread
+    __shared__ uint2 ringbuf[kTileThreads * kRingStride];
+    static_assert(sizeof(ringbuf) >= kTileCap * sizeof(uint16_t), "cell table");
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
@@ -390,18 +416,23 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
         if (threadIdx.x == 0 && M.ntargets) *fallback = epoch;
         return;
     }
-    tile_stage(TL, M, [&](uint32_t j) { return pos[j]; },
+    tile_stage(TL, M, (uint16_t*)ringbuf, [&](uint32_t j) { return pos[j]; },
                [&](uint32_t u, const int4& r, int ux, int uy, int uz) {
                    const int4 p = tile_rec(r, ux, uy, uz);
                    float4 f;
                    f.x = (float)(p.x - TL.cen[0] * (1 << kFixBits)) * C.fix_scale_f[0];
                    f.y = (float)(p.y - TL.cen[1] * (1 << kFixBits)) * C.fix_scale_f[1];
                    f.z = (float)(p.z - TL.cen[2] * (1 << kFixBits)) * C.fix_scale_f[2];
-                   f.w = 0.f;
+                   f.w = __int_as_float(ux + TL.uw * (uy + TL.uh * uz));
                    Pf[u] = f;
                });
     __syncthreads();
-    uint16_t* my = (uint16_t*)ring[threadIdx.x];
+    uint2* const myring = &ringbuf[threadIdx.x * kRingStride];
+    uint16_t* my = (uint16_t*)myring;
+    auto ring_octet = [&](uint32_t k8) {
+        const uint2 lo = myring[2 * (k8 & 1)], hi = myring[2 * (k8 & 1) + 1];
+        return make_uint4(lo.x, lo.y, hi.x, hi.y);
+    };
     uint32_t counted = 0;
     bool need_fb = false;
     const float cxf = (float)TL.cen[0], cyf = (float)TL.cen[1], czf = (float)TL.cen[2];
@@ -422,7 +453,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
         // exact predicate on the integer separation (candidate's record from
         // global memory, in the union frame)
         auto exact = [&](uint32_t u) {
-            const int c = M.cellof[u];
+            const int c = __float_as_int(Pf[u].w);
             const int4 pj = tile_rec(pos[M.gs[c] + (u - M.off[c])], c % ncu_w,
                                      (c / ncu_w) % TL.uh, c / ncu_wh);
             const Geom<float> g = pair_geom<3>(pi, pj, 0, 0, 0, 0, 0, 0, C);
@@ -490,11 +521,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
                 // an octet completed (at most one per group of four)
                 if ((cnt ^ c_in) & ~7u) {
                     const uint32_t k8 = c_in >> 3;
-                    if (k8 < (cap >> 3)) list[tile_octet(i, cap, k8)] = ring[threadIdx.x][k8 & 1];
+                    if (k8 < (cap >> 3)) list[tile_octet(i, cap, k8)] = ring_octet(k8);
                 }
             }
         }
-        if (cnt <= cap && (cnt & 7)) list[tile_octet(i, cap, cnt >> 3)] = ring[threadIdx.x][(cnt >> 3) & 1];
+        if (cnt <= cap && (cnt & 7)) list[tile_octet(i, cap, cnt >> 3)] = ring_octet(cnt >> 3);
         ncnt[i] = cnt;
         counted += cnt;
         need_fb |= cnt > cap;
@@ -515,13 +546,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_density(
     float2* __restrict__ rp, int with_eos) {
     __shared__ TileMeta M;
     __shared__ int4 Pi[kTileCap];
+    __shared__ uint16_t cellof[kTileCap];
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
     if (tile_empty(G, TL, c0, cstart, cend)) return;
     const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
     if (total > (uint32_t)cap_union) return;  // every target is the fallback's
-    tile_stage(TL, M, [&](uint32_t j) { return pos[j]; },
+    tile_stage(TL, M, cellof, [&](uint32_t j) { return pos[j]; },
                [&](uint32_t u, const int4& r, int ux, int uy, int uz) {
                    Pi[u] = tile_rec(r, ux, uy, uz);
                });
@@ -531,10 +563,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_density(
         int uc[3];
         tile_target(TL, M, t, &ui, &i, uc);
         const uint32_t cnt = ncnt[i];
+        const ListHead head = tile_list_head(list, i, cap);
         if (cnt > cap) continue;  // the fallback's
         const int4 pi = Pi[ui];
         double acc = 0.0;
-        tile_list_loop(list, i, cap, cnt, [&](uint32_t u) { return Pi[u]; },
+        tile_list_loop(list, i, cap, cnt, head, [&](uint32_t u) { return Pi[u]; },
                        [&](const int4& pj) {
                            const Geom<float> g = pair_geom<3>(pi, pj, 0, 0, 0, 0, 0, 0, C);
                            density_add<KERNEL, float>(acc, g, (double)rec_mass(pj), C);
@@ -560,6 +593,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
     __shared__ int4 Pi[kTileCap];
     __shared__ float4 V[kTileCap];
     __shared__ float2 RP[kTileCap];
+    __shared__ uint16_t cellof[kTileCap];
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
@@ -576,7 +610,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
             float4 v;
             float2 rp;
         };
-        tile_stage(TL, M, [&](uint32_t j) { return Rc{pos[j], vel[j], rp[j]}; },
+        tile_stage(TL, M, cellof, [&](uint32_t j) { return Rc{pos[j], vel[j], rp[j]}; },
                    [&](uint32_t u, const Rc& r, int ux, int uy, int uz) {
                        Pi[u] = tile_rec(r.p, ux, uy, uz);
                        V[u] = r.v;
@@ -587,9 +621,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
             uint32_t ui, i;
             int uc[3];
             tile_target(TL, M, t, &ui, &i, uc);
+            // every global load of the target up front: count, type, the
+            // list's first octets and the epilogue's state
             const uint32_t cnt = ncnt[i];
-            if (cnt > cap) continue;  // the fallback's
             const bool fluid = type[i] == 0;
+            const ListHead head = tile_list_head(list, i, cap);
+            const CloseIn ci = close_load<3>((int)i, St, drift, diag_part != nullptr);
+            if (cnt > cap) continue;  // the fallback's
             float acc[3] = {0.f, 0.f, 0.f};
             if (fluid) {
                 const int4 pi = Pi[ui];
@@ -601,7 +639,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
                     float4 v;
                     float2 rp;
                 };
-                tile_list_loop(list, i, cap, cnt, [&](uint32_t u) { return Nb{Pi[u], V[u], RP[u]}; },
+                tile_list_loop(list, i, cap, cnt, head,
+                               [&](uint32_t u) { return Nb{Pi[u], V[u], RP[u]}; },
                                [&](const Nb& b) {
                                    const Geom<float> g =
                                        pair_geom<3>(pi, b.p, 0, 0, 0, 0, 0, 0, C);
@@ -614,7 +653,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
             }
             double dv[4] = {0.0, 0.0, 0.0, 0.0};
             momentum_close<3, float>((int)i, acc, fluid, St, G, kick, drift, hdt, dt, key, counts,
-                                     flags, diag_part != nullptr, dv);
+                                     flags, diag_part != nullptr, dv, ci);
             for (int q = 0; q < 4; ++q) dsum[q] += dv[q];
         }
     }
