@@ -414,6 +414,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
     if (total > (uint32_t)cap_union) {
         tile_mark_overflow(M, ncnt);
         if (threadIdx.x == 0 && M.ntargets) *fallback = epoch;
+        // the counter is still touched: tile 0 raises the number of counters
+        // the reader sums
+        if (count_pairs) tile_count(0u, pairs, blk);
         return;
     }
     tile_stage(TL, M, (uint16_t*)ringbuf, [&](uint32_t j) { return pos[j]; },

@@ -96,10 +96,13 @@ def with_near_ties(p: W.Params, s: W.State, count: int, lo: float, hi: float,
 
 
 def shuffled(s: W.State, seed: int = 0) -> W.State:
-    """The same particles in a random order (ids travel with them)."""
+    """The same particles in a random order (ids, and densities where the
+    state carries them, travel with them)."""
     perm = np.random.default_rng(seed).permutation(s.n)
+    rho = getattr(s, "rho", None)
     return W.State(s.x[:, perm].copy(), s.u[:, perm].copy(), s.m[perm].copy(),
-                   s.ptype[perm].copy(), s.pid[perm].copy())
+                   s.ptype[perm].copy(), s.pid[perm].copy(),
+                   rho=None if rho is None else rho[perm].copy())
 
 
 def normwise(got: np.ndarray, ref: np.ndarray) -> float:
