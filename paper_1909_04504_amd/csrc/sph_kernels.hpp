@@ -1603,8 +1603,10 @@ __global__ __launch_bounds__(kBlock) void k_density(int n, Grid G, PairConst<T> 
 }
 
 // Per-particle state that momentum_close reads (u; x when it drifts; m for
-// the diagnostics), loaded by close_load; the tile pass loads it before its
-// pair loop so that the loads' latency hides behind the loop.
+// the diagnostics), loaded by close_load: the tile pass loads it before its
+// pair loop so that the loads' latency hides behind the loop (the list and
+// walk passes let momentum_close load it, which keeps their registers as
+// they were).
 struct CloseIn {
     double u[3], x[3], m;
 };
@@ -1621,7 +1623,7 @@ __device__ __forceinline__ CloseIn close_load(int i, const State& S, int drift, 
 }
 
 // Closing epilogue of the momentum pass for slot i with acceleration acc
-// (FP64, per particle, in registers; its loads come from close_load):
+// (FP64, per particle, in registers; its loads from close_load, if ci):
 //   kick  = 1: close the step, u = v + dt/2 a (walls: u = 0);
 //   dv: m|u|^2/2 and m u after it (for the diagnostics' block sums);
 //   drift = 1: open the next step (half kick, drift, wrap, hash and count),
@@ -1632,18 +1634,18 @@ __device__ __forceinline__ void momentum_close(int i, const T acc[3], bool fluid
                                                double dt, uint32_t* __restrict__ key,
                                                uint32_t* __restrict__ counts,
                                                uint32_t* __restrict__ flags, bool diag,
-                                               double dv[1 + DIM], const CloseIn& ci) {
+                                               double dv[1 + DIM], const CloseIn* ci = nullptr) {
     for (int k = 0; k < DIM; ++k) ((T*)S.a[k])[i] = acc[k];
     double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
     {
 #pragma clang fp contract(off)
         for (int k = 0; k < DIM; ++k) {
             a[k] = (double)acc[k];
-            const double uk = ci.u[k];
+            const double uk = ci ? ci->u[k] : S.u[k][i];
             u[k] = kick ? (fluid ? uk + hdt * a[k] : 0.0) : uk;
         }
         if (diag) {
-            const double m = ci.m;
+            const double m = ci ? ci->m : S.m[i];
             double u2 = 0.0;
             for (int k = 0; k < DIM; ++k) {
                 u2 += u[k] * u[k];
@@ -1653,7 +1655,8 @@ __device__ __forceinline__ void momentum_close(int i, const T acc[3], bool fluid
         }
     }
     if (drift) {
-        drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags, true, ci.x);
+        drift_and_hash<DIM>(i, S, G, fluid, u, a, hdt, dt, true, key, counts, flags, true,
+                            ci ? ci->x : nullptr);
     } else if (kick) {
         for (int k = 0; k < DIM; ++k) S.u[k][i] = u[k];
     }
@@ -1698,7 +1701,7 @@ __device__ __forceinline__ void momentum_one(
         acc[2] = az;
     }
     momentum_close<DIM, T>(i, acc, fluid, S, G, kick, drift, hdt, dt, key, counts, flags, diag,
-                           dv, close_load<DIM>(i, S, drift, diag));
+                           dv);
 }
 
 // Momentum equation for fluid particles (walls: a = 0), over the lists (or

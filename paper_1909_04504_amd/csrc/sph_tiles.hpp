@@ -656,7 +656,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
             }
             double dv[4] = {0.0, 0.0, 0.0, 0.0};
             momentum_close<3, float>((int)i, acc, fluid, St, G, kick, drift, hdt, dt, key, counts,
-                                     flags, diag_part != nullptr, dv, ci);
+                                     flags, diag_part != nullptr, dv, &ci);
             for (int q = 0; q < 4; ++q) dsum[q] += dv[q];
         }
     }
