@@ -307,10 +307,16 @@ __device__ __forceinline__ T kernel_f(T q, T sigma_h2) {
 }
 
 // F = (dW/dr)/r from |r|^2 with one reciprocal square root: rinv = 1/|r|,
-// q = |r| / h, 1/q = h rinv (rinv = 0 at r = 0, where F r = 0 anyway).
+// q = |r| / h, 1/q = h rinv.  At r = 0 the square root is taken of the
+// smallest normal number instead (every nonzero |r|^2 of a pair is far
+// above it), so rinv stays finite, q = 0 exactly and F is the inner
+// branch's value at q = 0, where F r = 0 anyway.
+template <typename T> __device__ __forceinline__ T tiny_normal();
+template <> __device__ __forceinline__ float tiny_normal<float>() { return 1.17549435e-38f; }
+template <> __device__ __forceinline__ double tiny_normal<double>() { return 2.2250738585072014e-308; }
 template <int KERNEL, typename T>
 __device__ __forceinline__ T kernel_f_r2(T r2, const PairConst<T>& C) {
-    const T rinv = r2 > T(0) ? p_rsqrt(r2) : T(0);
+    const T rinv = p_rsqrt(fmax(r2, tiny_normal<T>()));
     const T q = r2 * rinv * C.inv_h;
     if (KERNEL == 0) {
         const T t = T(2) - q;
@@ -1530,8 +1536,9 @@ __device__ __forceinline__ void density_add(double& acc, const Geom<T>& g, doubl
 // Momentum terms of pair (i, j) (eqs. mom:sph:press, mom:sph:visc):
 //   a_i += m_j [ -(P_i + P_j) F r_ij + 4 nu/(rho_i+rho_j) F |r|^2/(|r|^2 + eta h^2) v_ij ]
 // with F = (dW/dr)/r.  The self pair (j = i) is not skipped: r = 0 and
-// v_i - v_i = 0 multiply finite factors (F is finite at r = 0 and the viscous
-// factor is taken as 0 there), so it adds exactly zero, without a branch.
+// v_i - v_i = 0 multiply finite factors (F is finite at r = 0, and the
+// viscous factor holds |r|^2 = 0 over a positive denominator), so it adds
+// exactly zero, without a branch.
 template <int DIM, int KERNEL, typename T>
 __device__ __forceinline__ void momentum_add(T& ax, T& ay, T& az, const Geom<T>& g, T mj,
                                              const typename Vec4<T>::type& vi,
@@ -1542,8 +1549,7 @@ __device__ __forceinline__ void momentum_add(T& ax, T& ay, T& az, const Geom<T>&
     const T r2 = g.r2;
     const T F = kernel_f_r2<KERNEL, T>(r2, C);
     const T pres = -(rpi.y + rpj.y) * F;
-    const T visc = r2 > T(0) ? C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2))
-                             : T(0);
+    const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
     ax += mj * (pres * g.d[0] + visc * (vi.x - vj.x));
     ay += mj * (pres * g.d[1] + visc * (vi.y - vj.y));
     if (DIM == 3) az += mj * (pres * g.d[2] + visc * (vi.z - vj.z));
@@ -1790,9 +1796,7 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
                 const T rv = g.d[0] * vx + g.d[1] * vy + (DIM == 3 ? g.d[2] * vz : T(0));
                 if (fluid || tj == 0) ar += mj * (F * rv);
                 const T pres = -(rpi.y + pj.rp.y) * F;
-                const T visc = r2 > T(0) ? C.four_nu * F * r2 *
-                                               p_rcp((rpi.x + pj.rp.x) * (r2 + C.eta_h2))
-                                         : T(0);
+                const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + pj.rp.x) * (r2 + C.eta_h2));
                 ax += mj * (pres * g.d[0] + visc * vx);
                 ay += mj * (pres * g.d[1] + visc * vy);
                 if (DIM == 3) az += mj * (pres * g.d[2] + visc * vz);

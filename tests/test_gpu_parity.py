@@ -247,7 +247,7 @@ def test_mixed_precision_few_steps(case):
     out = dp.numpy()
     o = order_by_id(out["id"])
     assert normwise(out["rho"][o], ref["rho"]) < 1e-5
-    assert normwise(out["a"][:, o], ref["a"]) < 2e-4
+    assert normwise(out["a"][:, o], ref["a"]) < 1e-4
     assert normwise(out["u"][:, o], ref["u"]) < 1e-5
 
 
