@@ -233,15 +233,18 @@ __device__ __forceinline__ double p_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float p_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double p_rsqrt(double x) { return 1.0 / sqrt(x); }
 
-// FP64 square root for the mixed-precision density terms: an FP32 seed and
-// one Newton step, relative error ~2e-14 (sqrt(0) = 0).  The FP64 path uses
-// the correctly rounded sqrt.
+// FP64 square root for the mixed-precision density terms: an FP32
+// reciprocal square root y as the seed, r = x y, and one Newton step
+// r + (x - r^2) y / 2, relative error ~1e-14 (one transcendental instead of
+// a square root and a reciprocal).  x is taken at least the smallest normal
+// float, so that x = 0 (the self pair) gives r ~ 1e-19 instead of 0 * inf;
+// a kernel evaluated at q ~ 1e-19 / h rounds to its value at 0 (every
+// kernel here is flat there).  The FP64 path uses the correctly rounded sqrt.
 __device__ __forceinline__ double sqrt_newton(double x) {
-    const float s = __builtin_amdgcn_sqrtf((float)x);
-    const double sd = (double)s;
-    const double res = fma(-sd, sd, x);
-    const double corr = res * (0.5 * (double)__builtin_amdgcn_rcpf(s));
-    return s > 0.f ? sd + corr : 0.0;
+    const double xc = fmax(x, 1.1754943508222875e-38);
+    const double y = (double)__builtin_amdgcn_rsqf((float)xc);
+    const double r = xc * y;
+    return fma(fma(-r, r, xc), 0.5 * y, r);
 }
 __device__ __forceinline__ double density_sqrt(double x, float) { return sqrt_newton(x); }
 __device__ __forceinline__ double density_sqrt(double x, double) { return sqrt(x); }
