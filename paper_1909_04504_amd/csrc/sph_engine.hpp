@@ -524,6 +524,8 @@ sph::PairConst<T> pair_const(const sph_params* p, const sph::Grid& G) {
     C.R2 = (T)R2;
     C.R2_d = R2;
     C.inv_h_d = 1.0 / h;
+    C.half_inv_h_d = 0.5 / h;
+    C.two_inv_h_d = 2.0 / h;
     C.sigma_d = sigma;
     for (int k = 0; k < 3; ++k) {
         C.fix_scale[k] = G.cs[k] / (double)(1 << sph::kFixBits);

@@ -205,6 +205,7 @@ struct PairConst {
     T h;           // smoothing length
     double R2_d;         // (2h)^2 in FP64: the neighbour predicate
     double inv_h_d, sigma_d;  // FP64 density terms
+    double half_inv_h_d, two_inv_h_d;  // 1/(2h), 2/h: Wendland's factors in r
     double fix_scale[3];      // cell size / 2^27: one fixed-point unit
     float fix_scale_f[3];     // the same in FP32
     float R2_lo, R2_hi;       // (2h)^2 (1 -+ 1e-5): FP32 test band, FP64 inside it
@@ -280,6 +281,20 @@ __device__ __forceinline__ T kernel_w(T q, T sigma) {
         const T t2 = t * t;
         return sigma * (t2 * t2 * (T(2) * q + T(1)));
     }
+}
+
+// The density pass's form, in FP64: w(q) without sigma (the sum is scaled
+// once per particle), from r = |r_ij| (Wendland's two factors straight from
+// r, the splines through q = r/h).
+template <int KERNEL, typename T>
+__device__ __forceinline__ double kernel_w_r(double r, const PairConst<T>& C) {
+    if (KERNEL == 1) {
+        const double t = fma(-C.half_inv_h_d, r, 1.0);
+        const double u = fma(C.two_inv_h_d, r, 1.0);
+        const double t2 = t * t;
+        return t2 * t2 * u;
+    }
+    return kernel_w<KERNEL, double>(r * C.inv_h_d, 1.0);
 }
 
 // F(q) = (dW/dr) / r, so that grad_i W_ij = F r_ij.
@@ -1155,15 +1170,17 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
 }
 
 // ---------------------------------------------------------------------------
-// Density epilogue: store rho and, with_eos, p and (rho, P = p / rho^2),
+// Density epilogue: rho = sigma * wsum (wsum = sum of m_j w_ij from
+// density_add), stored with, if with_eos, p and (rho, P = p / rho^2),
 // computed in FP64 and rounded to the pair type.
 template <int DIM, typename T>
-__device__ __forceinline__ void finish_density(int i, double rho, const PairConst<T>& C,
+__device__ __forceinline__ void finish_density(int i, double wsum, const PairConst<T>& C,
                                                void* __restrict__ rho_out, int rho64,
                                                T* __restrict__ p_out,
                                                typename Vec4<T>::type* __restrict__ vel,
                                                typename Vec2<T>::type* __restrict__ rp,
                                                int with_eos) {
+    const double rho = C.sigma_d * wsum;
     store_rho<T>(rho_out, i, rho, rho64);
     if (with_eos) {
         const double p = tait64<T>(rho, C);
@@ -1528,12 +1545,13 @@ __global__ __launch_bounds__(kBlock) void k_nlist_walk(int n, Grid G, PairConst<
 // Pair terms shared by the list, walk and tile passes (one definition, so the
 // paths round alike; multiply-adds are fused within each statement only).
 //
-// Summation density (eq. 2), FP64 in both precisions: acc += m_j W(|r_ij|).
+// Summation density (eq. 2), FP64 in both precisions: acc += m_j w(|r_ij|),
+// the kernel without its normalisation sigma, which finish_density applies
+// to the sum.
 template <int KERNEL, typename T>
 __device__ __forceinline__ void density_add(double& acc, const Geom<T>& g, double mj,
                                             const PairConst<T>& C) {
-    const double q = density_sqrt(geom_r2d(g, C), T(0)) * C.inv_h_d;
-    acc += mj * kernel_w<KERNEL, double>(q, C.sigma_d);
+    acc += mj * kernel_w_r<KERNEL, T>(density_sqrt(geom_r2d(g, C), T(0)), C);
 }
 
 // Momentum terms of pair (i, j) (eqs. mom:sph:press, mom:sph:visc):
@@ -1553,9 +1571,17 @@ __device__ __forceinline__ void momentum_add(T& ax, T& ay, T& az, const Geom<T>&
     const T F = kernel_f_r2<KERNEL, T>(r2, C);
     const T pres = -(rpi.y + rpj.y) * F;
     const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
-    ax += mj * (pres * g.d[0] + visc * (vi.x - vj.x));
-    ay += mj * (pres * g.d[1] + visc * (vi.y - vj.y));
-    if (DIM == 3) az += mj * (pres * g.d[2] + visc * (vi.z - vj.z));
+    // m_j folded into the two factors once per pair; each component takes
+    // two multiply-adds, the pressure term first
+    const T mp = mj * pres, mv = mj * visc;
+    ax += mp * g.d[0];
+    ax += mv * (vi.x - vj.x);
+    ay += mp * g.d[1];
+    ay += mv * (vi.y - vj.y);
+    if (DIM == 3) {
+        az += mp * g.d[2];
+        az += mv * (vi.z - vj.z);
+    }
 }
 
 // Summation density (eq. 2) of sorted slot i and, if with_eos, the Tait EOS
@@ -1800,9 +1826,15 @@ __global__ __launch_bounds__(kBlock) void k_cont_momentum(
                 if (fluid || tj == 0) ar += mj * (F * rv);
                 const T pres = -(rpi.y + pj.rp.y) * F;
                 const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + pj.rp.x) * (r2 + C.eta_h2));
-                ax += mj * (pres * g.d[0] + visc * vx);
-                ay += mj * (pres * g.d[1] + visc * vy);
-                if (DIM == 3) az += mj * (pres * g.d[2] + visc * vz);
+                const T mp = mj * pres, mv = mj * visc;
+                ax += mp * g.d[0];
+                ax += mv * vx;
+                ay += mp * g.d[1];
+                ay += mv * vy;
+                if (DIM == 3) {
+                    az += mp * g.d[2];
+                    az += mv * vz;
+                }
             });
         const T acc[3] = {ax, ay, az};
         double u[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};

@@ -147,7 +147,9 @@ def test_tiles_with_particle_outside_box():
 def test_tiled_rollout_gradient_equal():
     """The adjoint recomputes its steps through the tiled passes and rebuilds
     global lists for its own pair passes: the rollout gradient is bitwise
-    that of the untiled run."""
+    that of the untiled run.  The kinetic energy comes from the diagnostics,
+    whose per-tile partial sums add in another order than the per-block
+    ones: equal to 1e-13."""
     from paper_1909_04504_amd.autograd import rollout_ke
     p, s = case("cube_cd2")
     res = []
@@ -158,7 +160,7 @@ def test_tiled_rollout_gradient_equal():
         ke = rollout_ke(u0, nu, pp, s.x, s.m, s.ptype, 6, 3, MIXED, pair_tiles=tiles)
         ke.backward()
         res.append((float(ke.detach()), u0.grad.cpu().numpy(), float(nu.grad)))
-    assert res[0][0] == res[1][0]
+    assert res[0][0] == pytest.approx(res[1][0], rel=1e-13)
     assert np.array_equal(res[0][1], res[1][1])
     assert res[0][2] == res[1][2]
 
