@@ -1314,8 +1314,6 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
     constexpr int kSegs = (DIM == 3 ? NR : 1) * NR * 2;
     static_assert(kSegs <= 64, "one lane per stencil segment");
     const int lane = (int)(threadIdx.x & 63);
-    const int wv = (int)(threadIdx.x >> 6);
-    __shared__ float tco[kBlock / 64][DIM][64];
     const int blk = xcd_block();
     const uint64_t wave = (uint64_t)blk * (kBlock / 64) + (threadIdx.x >> 6);
     // this wave's cells, one per lane: lane l takes cell w per_wave + l, or
@@ -1416,11 +1414,6 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
             }
             // with a far target in the group, every pair takes the exact test
             const bool gfar = kFp64 && __ballot(tfar && (uint32_t)lane < nt) != 0ull;
-            // the targets' coordinates, read back by every lane as LDS
-            // broadcasts (the wave's own slice; its LDS accesses stay in order)
-            __builtin_amdgcn_wave_barrier();
-            for (int k = 0; k < DIM; ++k) tco[wv][k][lane] = tf[k];
-            __builtin_amdgcn_wave_barrier();
             uint32_t cntv = 0;  // lane t: count of target g0 + t
             // this lane's candidate in the current chunk and its stencil data
             uint32_t cj = 0;
@@ -1445,7 +1438,11 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
                 // target, so neither test below accepts it
                 if (!valid) cf[0] = __builtin_huge_valf();
                 for (uint32_t t = 0; t < nt; ++t) {
-                    auto tcoord = [&](int k) { return tco[wv][k][t]; };
+                    // target t's coordinates, read from its lane
+                    auto tcoord = [&](int k) {
+                        return __int_as_float(
+                            __builtin_amdgcn_readlane(__float_as_int(tf[k]), (int)t));
+                    };
                     const float dx = tcoord(0) - cf[0], dy = tcoord(1) - cf[1];
                     float r2 = dx * dx + dy * dy;
                     if (DIM == 3) {
