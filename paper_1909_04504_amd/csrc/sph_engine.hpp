@@ -249,9 +249,12 @@ inline uint32_t list_cap(const sph_params* p, int64_t n) {
 }
 
 // Tiles of the 3D mixed-precision summation passes (ntiles = 0: not used).
-// Boxes of 8 x 4 x 4 cells with half-size cells (a union of 12 x 8 x 8
-// cells, about 2,600 particles on the 256^3 lattice at h = 1.5 dx), and of
-// 4 x 4 x 2 or 2 x 2 x 2 whole cells (by the mean occupancy).  By default
+// Boxes of 6 x 6 x 4 cells with half-size cells (about 490 targets for the
+// 512 threads; a union of 10 x 10 x 8 cells, about 2,700 particles on the
+// 256^3 lattice at h = 1.5 dx; measured against 8 x 4 x 4, 4 x 6 x 6,
+// 6 x 4 x 6, 7 x 5 x 4 and 8 x 6 x 3 boxes: 13.6 against 14.5, 13.8, 13.7,
+// 14.3 and 15.3 ms per cube step), and of 4 x 4 x 2 or 2 x 2 x 2 whole
+// cells (by the mean occupancy).  By default
 // (pair_tiles = 0) only on dense grids, at least one particle per cell on
 // average: on a sparse grid most boxes hold few particles, and the lists in
 // global memory stay cache-resident (3D dam break, 2.18M particles on 5.4M
@@ -266,7 +269,7 @@ inline sph::Tiles make_tiles(const sph_params* p, const sph::Grid& G, int64_t n,
     if (p->pair_tiles == 0 && n < ncells) return T;
     T.S = G.S;
     if (T.S == 2) {
-        T.tw = 8; T.th = 4; T.td = 4;
+        T.tw = 6; T.th = 6; T.td = 4;
     } else if ((double)n / (double)ncells <= 19.0) {
         T.tw = 4; T.th = 4; T.td = 2;
     } else {

@@ -40,7 +40,7 @@ namespace sph {
 
 constexpr int kTileThreads = 512;                // 8 waves per workgroup
 constexpr int kTileCellsMax = 1024;              // union cells per tile (two per thread)
-constexpr int kTileTargetCellsMax = 128;         // target cells per tile
+constexpr int kTileTargetCellsMax = 160;         // target cells per tile
 constexpr int kTileCap = 3072;                   // union particles staged in LDS
 constexpr int kTileUnionAxisMax = 12;            // union cells per axis: 12 * 2^27 + 2^29 < 2^31
 constexpr uint32_t kTileOverflow = 0xffffffffu;  // count of a target left to the fallback

@@ -26,7 +26,7 @@ FIELDS = ("x", "u", "a", "rho", "p", "id")
 def case(name):
     if name == "cube_cd1":      # 4 cells per axis: every union wraps onto itself
         return W.periodic_cube(n_side=14, jitter=0.3, sigma_u=0.1, seed=13)
-    if name == "cube_cd2":      # 9 cells per axis, boxes of 8 x 4 x 4
+    if name == "cube_cd2":      # 9 cells per axis, boxes of 6 x 6 x 4
         return W.periodic_cube(n_side=14, jitter=0.3, sigma_u=0.1, seed=14, cell_div=2)
     if name == "cube32_cd2":    # 21 cells per axis: partial boxes at the edge
         return W.periodic_cube(n_side=32, jitter=0.2, sigma_u=0.1, seed=21, cell_div=2)
