@@ -325,16 +325,22 @@ __device__ __forceinline__ T kernel_f(T q, T sigma_h2) {
 }
 
 // F = (dW/dr)/r from |r|^2 with one reciprocal square root: rinv = 1/|r|,
-// q = |r| / h, 1/q = h rinv.  At r = 0 the square root is taken of the
-// smallest normal number instead (every nonzero |r|^2 of a pair is far
-// above it), so rinv stays finite, q = 0 exactly and F is the inner
-// branch's value at q = 0, where F r = 0 anyway.
+// q = |r| / h, 1/q = h rinv.  At r = 0 (the self pair), F r = 0 anyway.
+// In FP32 the square root is then taken of the smallest normal number
+// instead (every nonzero |r|^2 of a pair is far above it), so rinv stays
+// finite, q = 0 exactly and F is the inner branch's value at q = 0: no
+// select.  In FP64 rinv is set to 0 there by a select, which measured
+// faster than the clamp (the FP64 square root is a software sequence).
 template <typename T> __device__ __forceinline__ T tiny_normal();
 template <> __device__ __forceinline__ float tiny_normal<float>() { return 1.17549435e-38f; }
 template <> __device__ __forceinline__ double tiny_normal<double>() { return 2.2250738585072014e-308; }
 template <int KERNEL, typename T>
 __device__ __forceinline__ T kernel_f_r2(T r2, const PairConst<T>& C) {
-    const T rinv = p_rsqrt(fmax(r2, tiny_normal<T>()));
+    T rinv;
+    if constexpr (sizeof(T) == 8)
+        rinv = r2 > T(0) ? p_rsqrt(r2) : T(0);
+    else
+        rinv = p_rsqrt(fmax(r2, tiny_normal<T>()));
     const T q = r2 * rinv * C.inv_h;
     if (KERNEL == 0) {
         const T t = T(2) - q;
@@ -1170,9 +1176,10 @@ __global__ __launch_bounds__(kBlock) void k_pack(int n, State S, Grid G,
 }
 
 // ---------------------------------------------------------------------------
-// Density epilogue: rho = sigma * wsum (wsum = sum of m_j w_ij from
-// density_add), stored with, if with_eos, p and (rho, P = p / rho^2),
-// computed in FP64 and rounded to the pair type.
+// Density epilogue: rho from the sum of density_add (in mixed precision
+// the sum of m_j w_ij, scaled here by sigma; in FP64 the sum of m_j W_ij
+// itself), stored with, if with_eos, p and (rho, P = p / rho^2), computed
+// in FP64 and rounded to the pair type.
 template <int DIM, typename T>
 __device__ __forceinline__ void finish_density(int i, double wsum, const PairConst<T>& C,
                                                void* __restrict__ rho_out, int rho64,
@@ -1180,7 +1187,7 @@ __device__ __forceinline__ void finish_density(int i, double wsum, const PairCon
                                                typename Vec4<T>::type* __restrict__ vel,
                                                typename Vec2<T>::type* __restrict__ rp,
                                                int with_eos) {
-    const double rho = C.sigma_d * wsum;
+    const double rho = sizeof(T) == 8 ? wsum : C.sigma_d * wsum;  // see density_add
     store_rho<T>(rho_out, i, rho, rho64);
     if (with_eos) {
         const double p = tait64<T>(rho, C);
@@ -1542,21 +1549,29 @@ __global__ __launch_bounds__(kBlock) void k_nlist_walk(int n, Grid G, PairConst<
 // Pair terms shared by the list, walk and tile passes (one definition, so the
 // paths round alike; multiply-adds are fused within each statement only).
 //
-// Summation density (eq. 2), FP64 in both precisions: acc += m_j w(|r_ij|),
-// the kernel without its normalisation sigma, which finish_density applies
-// to the sum.
+// Summation density (eq. 2), FP64 terms in both precisions.  Mixed
+// precision: acc += m_j w(|r_ij|), the kernel without its normalisation
+// sigma (finish_density scales the sum), Wendland's factors straight from
+// r.  FP64: acc += m_j W(q) with q = |r_ij|/h, the normalised kernel; in
+// the FP64 list pass this form keeps the kernel at 96 registers (five
+// waves per SIMD), the other measured 10% slower there.
 template <int KERNEL, typename T>
 __device__ __forceinline__ void density_add(double& acc, const Geom<T>& g, double mj,
                                             const PairConst<T>& C) {
-    acc += mj * kernel_w_r<KERNEL, T>(density_sqrt(geom_r2d(g, C), T(0)), C);
+    const double r = density_sqrt(geom_r2d(g, C), T(0));
+    if constexpr (sizeof(T) == 8)
+        acc += mj * kernel_w<KERNEL, double>(r * C.inv_h_d, C.sigma_d);
+    else
+        acc += mj * kernel_w_r<KERNEL, T>(r, C);
 }
 
 // Momentum terms of pair (i, j) (eqs. mom:sph:press, mom:sph:visc):
 //   a_i += m_j [ -(P_i + P_j) F r_ij + 4 nu/(rho_i+rho_j) F |r|^2/(|r|^2 + eta h^2) v_ij ]
 // with F = (dW/dr)/r.  The self pair (j = i) is not skipped: r = 0 and
 // v_i - v_i = 0 multiply finite factors (F is finite at r = 0, and the
-// viscous factor holds |r|^2 = 0 over a positive denominator), so it adds
-// exactly zero, without a branch.
+// viscous factor holds |r|^2 = 0 over a positive denominator in FP32 and
+// is set to 0 by a select in FP64, the faster form in each), so it adds
+// exactly zero.
 template <int DIM, int KERNEL, typename T>
 __device__ __forceinline__ void momentum_add(T& ax, T& ay, T& az, const Geom<T>& g, T mj,
                                              const typename Vec4<T>::type& vi,
@@ -1567,7 +1582,8 @@ __device__ __forceinline__ void momentum_add(T& ax, T& ay, T& az, const Geom<T>&
     const T r2 = g.r2;
     const T F = kernel_f_r2<KERNEL, T>(r2, C);
     const T pres = -(rpi.y + rpj.y) * F;
-    const T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
+    T visc = C.four_nu * F * r2 * p_rcp((rpi.x + rpj.x) * (r2 + C.eta_h2));
+    if constexpr (sizeof(T) == 8) visc = r2 > T(0) ? visc : T(0);
     // m_j folded into the two factors once per pair; each component takes
     // two multiply-adds, the pressure term first
     const T mp = mj * pres, mv = mj * visc;
