@@ -695,8 +695,13 @@ struct Engine {
             // cell-cooperative build in 2D with cells of 2h (about 7 targets
             // and 61 candidates per cell); the walk build elsewhere, where a
             // cell's candidates are many times a wave (measured: 3D dam break
-            // 0.88 ms walk at cell_div 2 against 2.6 ms cooperative at 1)
-            if (DIM == 2 && decltype(R)::value == 1) {
+            // 0.88 ms walk at cell_div 2 against 2.6 ms cooperative at 1).
+            // The cooperative build addresses the list with 32-bit byte
+            // offsets: lists of 4 GiB or more take the walk build.
+            const bool small_list = (uint64_t)4 * L.cap * sph::kListTile *
+                                        (((uint64_t)n + sph::kListTile - 1) / sph::kListTile) <
+                                    ((uint64_t)1 << 32);
+            if (DIM == 2 && decltype(R)::value == 1 && small_list) {
                 const NlistShape sh = nlist_shape(n, ncells);
                 launch(K_NLIST, sph::k_nlist<DIM, decltype(R)::value, T>, sh.blocks, st, n,
                        (uint32_t)ncells, sh.per_wave, sh.by_slots, G, C, skey(), pos(), cs, ce,

@@ -1277,6 +1277,12 @@ __device__ __forceinline__ float filt_cand(const double4& r, int k, int, int w,
     return (float)((v + (w == 0 ? 0.0 : (w < 0 ? -C.L[k] : C.L[k]))) - centre);
 }
 
+// v_writelane: value into lane `lane` of old (the other lanes keep theirs).
+__device__ int amdgcn_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ uint32_t lane_write(uint32_t value, int lane, uint32_t old) {
+    return (uint32_t)amdgcn_writelane_i32((int)value, lane, (int)old);
+}
+
 // Neighbour lists of all particles (Sec. 2.2), built cell by cell.  Wave w
 // takes per_wave (<= 64) consecutive cells from w per_wave on (dense grids),
 // or, with by_slots, the cells whose first sorted slot lies in
@@ -1422,6 +1428,11 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
             // with a far target in the group, every pair takes the exact test
             const bool gfar = kFp64 && __ballot(tfar && (uint32_t)lane < nt) != 0ull;
             uint32_t cntv = 0;  // lane t: count of target g0 + t
+            // lane t: byte offset of target g0 + t's column in the list (entry
+            // k of slot u at u + 64 (k + (u / 64)(cap - 1)) words; the host
+            // keeps the list below 4 GiB for this kernel)
+            const uint32_t ul = g0 + (uint32_t)lane;
+            const uint32_t colv = 4u * ((ul / kListTile) * cap * kListTile + ul % kListTile);
             // this lane's candidate in the current chunk and its stencil data
             uint32_t cj = 0;
             int valid = 0, cmeta = 0, cxoff = 0;
@@ -1460,26 +1471,27 @@ __global__ __launch_bounds__(kBlock) void k_nlist(int n, uint32_t ncells, uint32
                     // accepted by the exact predicate.  r2 - mid is exact near
                     // the band (Sterbenz), so |r2 - mid| < w holds on all of
                     // [R2_lo, R2_hi] and a little beyond, where the exact test
-                    // decides alike.
+                    // decides alike.  The mask is taken from the compare itself
+                    // (no per-lane flag to convert) unless the band needs the
+                    // exact test.
                     bool acc = r2 < C.R2_lo;
+                    unsigned long long m = __builtin_amdgcn_ballot_w64(r2 < C.R2_lo);
                     const bool band = exact_all || fabsf(r2 - C.R2_mid) < C.R2_w;
                     if (__builtin_amdgcn_ballot_w64(band)) {
                         const R ri = rec_bcast<DIM>(tr, (int)t);
                         const Geom<T> gm = pair_geom<DIM>(ri, rj, ox, oy, oz, wx, wy, wz, C);
                         acc = acc || (band && geom_r2d(gm, C) < C.R2_d);
+                        m = __builtin_amdgcn_ballot_w64(acc);
                     }
-                    const unsigned long long m = __builtin_amdgcn_ballot_w64(acc);
+                    // entry k of target t, written by the accepted lane of rank
+                    // k - base; the count kept in lane t
                     const uint32_t base = __builtin_amdgcn_readlane(cntv, t);
-                    if (acc) {
-                        const uint32_t k = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
-                        // entry k of slot u = g0 + t: list + u + 64 (k + (u / 64)(cap - 1))
-                        const uint32_t u = g0 + t;
-                        uint32_t* __restrict__ lt =
-                            list + u + (size_t)(u / kListTile) * (size_t)(cap - 1) * kListTile;
-                        if (k < cap) lt[k * kListTile] = word;
-                    }
-                    if ((uint32_t)lane == t) cntv = base + (uint32_t)__popcll(m);
+                    const uint32_t colb = __builtin_amdgcn_readlane(colv, t);
+                    const uint32_t k = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, base));
+                    if (acc && k < cap)
+                        *(uint32_t*)((char*)list + (colb + k * (uint32_t)(4 * kListTile))) = word;
+                    cntv = lane_write(base + (uint32_t)__popcll(m), (int)t, cntv);
                 }
                 valid = 0;
                 fill = 0;
