@@ -45,6 +45,14 @@ def make_case(name):
     if name == "cube3d_quintic":
         p, s = W.periodic_cube(n_side=16, jitter=0.3, sigma_u=0.1, seed=18, hdx=1.0)
         return p.replace(kernel=W.QUINTIC), s
+    if name == "tg2d_wide":
+        # cells of 4 dx: about 16 targets and 144 candidates per cell, so the
+        # 2D cooperative build takes each cell's candidates in several
+        # passes of 64
+        return W.taylor_green(40, jitter=0.3, seed=20, hdx=2.0)
+    if name == "tg2d_dense":
+        # cells of 6 dx: about 36 targets and 324 candidates per cell
+        return W.taylor_green(30, jitter=0.3, seed=21, hdx=3.0)
     if name == "sparse2d":
         # a small jittered patch in a large non-periodic box: more cells than
         # particles, so the list build takes its cells from the sorted slots
@@ -63,7 +71,7 @@ def make_case(name):
 
 
 CASES = ["tg2d", "tg2d_cd2", "cube3d", "cube3d_cd2", "dam3d", "box2d", "tg2d_quintic",
-         "cube3d_quintic", "sparse2d"]
+         "cube3d_quintic", "sparse2d", "tg2d_wide", "tg2d_dense"]
 
 
 def gpu_sorted(p, s, prec):
@@ -353,7 +361,8 @@ def step_interactions(p, s, prec, cap):
     return sph.read_interactions(ws, reset=True), dp.numpy()
 
 
-BAND_CASES = ["tg2d", "tg2d_cd2", "cube3d", "cube3d_cd2", "tg2d_quintic", "sparse2d", "box2d"]
+BAND_CASES = ["tg2d", "tg2d_cd2", "cube3d", "cube3d_cd2", "tg2d_quintic", "sparse2d", "box2d",
+              "tg2d_wide", "tg2d_dense"]
 
 
 @pytest.mark.parametrize("case", BAND_CASES)
