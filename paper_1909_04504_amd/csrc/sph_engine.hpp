@@ -378,8 +378,11 @@ struct NlistShape {
 inline NlistShape nlist_shape(int64_t n, int64_t ncells) {
     const int64_t per_block = sph::kBlock / 64;
     if (ncells <= n) {
-        const int64_t waves = (ncells + kNlistCells - 1) / kNlistCells;
-        return {(unsigned)((waves + per_block - 1) / per_block), kNlistCells, 0};
+        // grids of up to 65,536 cells take one cell per wave: more waves on a
+        // small grid (512^2: build 33.2 -> 32.7 us)
+        const uint32_t per = ncells <= 65536 ? 1u : kNlistCells;
+        const int64_t waves = (ncells + per - 1) / per;
+        return {(unsigned)((waves + per_block - 1) / per_block), per, 0};
     }
     const int64_t waves = (n + kNlistSlots - 1) / kNlistSlots;
     return {(unsigned)((waves + per_block - 1) / per_block), kNlistSlots, 1};
