@@ -356,7 +356,8 @@ struct Layout {
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Launch shape of the cell-cooperative list build.  Dense grids (no more
-// cells than particles): kNlistCells consecutive cells per wave, each wave
+// cells than particles): one cell per wave up to 65,536 cells, above that
+// kNlistCells consecutive cells per wave, each wave
 // overlapping the range loads of its next cell with the current one; short
 // waves also finish the list rows they share before those leave L2
 // (measured, 512^2 / 1024^2 / 2048^2 lattices: 1 cell 36.4 / 117 / 489 us,
@@ -378,8 +379,8 @@ struct NlistShape {
 inline NlistShape nlist_shape(int64_t n, int64_t ncells) {
     const int64_t per_block = sph::kBlock / 64;
     if (ncells <= n) {
-        // grids of up to 65,536 cells take one cell per wave: more waves on a
-        // small grid (512^2: build 33.2 -> 32.7 us)
+        // one cell per wave on small grids: more waves (512^2: build 33.2 ->
+        // 32.7 us with the current per-target loop)
         const uint32_t per = ncells <= 65536 ? 1u : kNlistCells;
         const int64_t waves = (ncells + per - 1) / per;
         return {(unsigned)((waves + per_block - 1) / per_block), per, 0};
