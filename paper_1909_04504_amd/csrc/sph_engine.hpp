@@ -106,6 +106,22 @@ struct Timer {
 };
 inline Timer g_timer;
 
+// Compute units of the current device, looked up once per device (256 if
+// the runtime cannot say).
+inline unsigned device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return (unsigned)v;
+}
+
 // Launches kernel k on stream st with grid blocks of kBlock threads.  While
 // timing is on, the launch carries start and stop events recorded by the
 // dispatch itself (hipExtLaunchKernel), so the elapsed time is the kernel's
@@ -769,12 +785,15 @@ struct Engine {
             const unsigned fb = fallback_blocks(n);
             const int stride = TL.ntiles + (int)fb;
             double* part = diag_out ? (double*)(ws + L.diag) : nullptr;
+            // one workgroup per CU (the staging's LDS), each over every
+            // wgs-th tile
+            const unsigned wgs = std::min<unsigned>((unsigned)TL.ntiles, device_cus());
             with_reach([&](auto R) {
-                launch_b(K_TILE_MOMENTUM, sph::k_tile_momentum<decltype(R)::value, KERNEL>,
-                         (unsigned)TL.ntiles, sph::kTileThreads, st, n, G, C, TL, TL.cap, pos(),
-                         vel(), rp(), s.type, cs, ce, tcap(), (const uint4*)list(), lcnt(), s,
-                         kick ? 1 : 0, drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(),
-                         flags(), part, stride);
+                launch_b(K_TILE_MOMENTUM, sph::k_tile_momentum<decltype(R)::value, KERNEL>, wgs,
+                         sph::kTileThreads, st, n, G, C, TL, TL.cap, pos(), vel(), rp(), s.type,
+                         cs, ce, tcap(), (const uint4*)list(), lcnt(), s, kick ? 1 : 0,
+                         drift ? 1 : 0, 0.5 * prm->dt, prm->dt, key(), counts(), flags(), part,
+                         stride);
             });
             SPH_TRY(launch_check("k_tile_momentum"));
             with_reach([&](auto R) {

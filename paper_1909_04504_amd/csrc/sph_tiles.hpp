@@ -134,12 +134,56 @@ __device__ __forceinline__ bool tile_empty(const Grid& G, const Tiles& TL, const
     return se[1] <= se[0];
 }
 
-// Cell ranges of the union, their scan, and the target cells.  Returns the
-// number of union particles (every thread).
-__device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, const int c0[3],
-                                               const uint32_t* __restrict__ cstart,
-                                               const uint32_t* __restrict__ cend, int n,
-                                               TileMeta& M) {
+// Cell ranges of the union, their scan, and the target cells, in two
+// halves: tile_setup_loads issues each thread's loads (union cells 2t and
+// 2t + 1), tile_setup_finish forms the counts, the scans and the target
+// cells from them (so that a pass can have the loads in flight while it
+// works on another tile).
+struct SetupLoads {
+    uint32_t s[2], e[2];
+    bool in[2];
+};
+// Marks a loaded value as used here and not before: the compiler otherwise
+// moves its first use (and the wait for the load) up to where the load was
+// issued, ahead of loads that were meant to overlap it.
+template <typename V>
+__device__ __forceinline__ void keep_in_flight(V& v) {
+    static_assert(sizeof(V) % 4 == 0, "whole registers");
+    uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(V) / 4); ++k) asm volatile("" : "+v"(w[k]));
+}
+__device__ __forceinline__ SetupLoads tile_setup_loads(const Grid& G, const Tiles& TL,
+                                                       const int c0[3],
+                                                       const uint32_t* __restrict__ cstart,
+                                                       const uint32_t* __restrict__ cend) {
+    const int ncu = TL.uw * TL.uh * TL.ud;
+    SetupLoads r;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = 2 * (int)threadIdx.x + q;
+        r.s[q] = r.e[q] = 0;
+        r.in[q] = false;
+        if (c < ncu) {
+            const int ux = c % TL.uw, uy = (c / TL.uw) % TL.uh, uz = c / (TL.uw * TL.uh);
+            const int gx = tile_axis(G, 0, c0[0], ux, TL.S);
+            const int gy = tile_axis(G, 1, c0[1], uy, TL.S);
+            const int gz = tile_axis(G, 2, c0[2], uz, TL.S);
+            if (gx >= 0 && gy >= 0 && gz >= 0) {
+                const int gc[3] = {gx, gy, gz};
+                const uint32_t key = cell_key(gc, G);
+                r.s[q] = cstart[key];
+                r.e[q] = cend[key];
+                r.in[q] = true;
+            }
+        }
+    }
+    return r;
+}
+// Returns the number of union particles (every thread).
+__device__ __forceinline__ uint32_t tile_setup_finish(const Grid& G, const Tiles& TL,
+                                                      const int c0[3], int n,
+                                                      const SetupLoads& r, TileMeta& M) {
     const int ncu = TL.uw * TL.uh * TL.ud;
     uint32_t cnt[2];
 #pragma unroll
@@ -147,17 +191,10 @@ __device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, c
         const int c = 2 * (int)threadIdx.x + q;
         cnt[q] = 0;
         if (c < ncu) {
-            const int ux = c % TL.uw, uy = (c / TL.uw) % TL.uh, uz = c / (TL.uw * TL.uh);
-            const int gx = tile_axis(G, 0, c0[0], ux, TL.S);
-            const int gy = tile_axis(G, 1, c0[1], uy, TL.S);
-            const int gz = tile_axis(G, 2, c0[2], uz, TL.S);
             uint32_t s = 0;
-            if (gx >= 0 && gy >= 0 && gz >= 0) {
-                const int gc[3] = {gx, gy, gz};
-                const uint32_t key = cell_key(gc, G);
-                s = cstart[key];
-                uint32_t e = cend[key];
-                e = e < (uint32_t)n ? e : (uint32_t)n;
+            if (r.in[q]) {
+                s = r.s[q];
+                const uint32_t e = r.e[q] < (uint32_t)n ? r.e[q] : (uint32_t)n;
                 cnt[q] = e > s ? e - s : 0u;
             }
             M.gs[c] = s;
@@ -182,19 +219,19 @@ __device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, c
     const int thc = min(TL.th, G.nc[1] - c0[1]);
     const int tdc = min(TL.td, G.nc[2] - c0[2]);
     const int ntc = twc * thc * tdc;
-    const int r = (int)threadIdx.x;
+    const int rr = (int)threadIdx.x;
     uint32_t tcnt = 0;
     int tcell = 0;
-    if (r < ntc) {
-        const int x = r % twc, y = (r / twc) % thc, z = r / (twc * thc);
+    if (rr < ntc) {
+        const int x = rr % twc, y = (rr / twc) % thc, z = rr / (twc * thc);
         tcell = (TL.S + x) + TL.uw * ((TL.S + y) + TL.uh * (TL.S + z));
         tcnt = M.off[tcell + 1] - M.off[tcell];
     }
     uint32_t ntargets;
     const uint32_t tpre = tile_scan2(tcnt, 0u, M, &ntargets);
-    if (r < ntc) {
-        M.tc[r] = tcell;
-        M.tpre[r] = tpre;
+    if (rr < ntc) {
+        M.tc[rr] = tcell;
+        M.tpre[rr] = tpre;
     }
     if (threadIdx.x == 0) {
         M.tpre[ntc] = ntargets;
@@ -203,6 +240,12 @@ __device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, c
     }
     __syncthreads();
     return total;
+}
+__device__ __forceinline__ uint32_t tile_setup(const Grid& G, const Tiles& TL, const int c0[3],
+                                               const uint32_t* __restrict__ cstart,
+                                               const uint32_t* __restrict__ cend, int n,
+                                               TileMeta& M) {
+    return tile_setup_finish(G, TL, c0, n, tile_setup_loads(G, TL, c0, cstart, cend), M);
 }
 
 // Target t of the tile: its union index, global slot and union cell coords.
@@ -234,39 +277,59 @@ __device__ __forceinline__ void tile_mark_overflow(const TileMeta& M, uint32_t* 
 
 // Stages the union's records: store(u, load(j), ux, uy, uz) for union
 // particle u held in global slot j of union cell (ux, uy, uz).  The cell of
-// every union index is noted first, so that each thread then loads four
-// particles at a time (independent loads in flight) at indices t, t + 512, ...
-// (kTileCap <= 8 * kTileThreads: a single round).  cellof: kTileCap entries
-// of LDS, the union cell of each staged particle (free again on return).
-template <typename Load, typename Store>
-__device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, uint16_t* cellof,
-                                           Load&& load, Store&& store) {
+// every union index is noted first (tile_cellof), so that each thread then
+// loads its particles at indices t, t + 512, ... with all loads in flight
+// (tile_stage_loads; kTileCap <= 8 * kTileThreads: a single round) and
+// stores them (tile_stage_store).  cellof: kTileCap entries of LDS, the
+// union cell of each staged particle.
+__device__ __forceinline__ void tile_cellof(const Tiles& TL, const TileMeta& M,
+                                            uint16_t* cellof) {
     const int ncu = TL.uw * TL.uh * TL.ud;
     for (int c = threadIdx.x; c < ncu; c += kTileThreads)
         for (uint32_t u = M.off[c]; u < M.off[c + 1]; ++u) cellof[u] = (uint16_t)c;
     __syncthreads();
+}
+constexpr int kStageQ = (kTileCap + kTileThreads - 1) / kTileThreads;
+static_assert(kStageQ <= 8, "staging registers");
+template <typename P>
+struct StageRegs {
+    P v[kStageQ];
+};
+template <typename P, typename Load>
+__device__ __forceinline__ void tile_stage_loads(const TileMeta& M, const uint16_t* cellof,
+                                                 Load&& load, StageRegs<P>& R) {
     const uint32_t total = M.total;
-    using P = decltype(load(0u));
-    constexpr int kQ = (kTileCap + kTileThreads - 1) / kTileThreads;
-    static_assert(kQ <= 8, "staging registers");
-    for (uint32_t b = threadIdx.x; b < total; b += kQ * kTileThreads) {
-        P v[kQ];
-        int cq[kQ];
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const uint32_t u = b + (uint32_t)q * kTileThreads;
-            cq[q] = u < total ? (int)cellof[u] : 0;
-            if (u < total) v[q] = load(M.gs[cq[q]] + (u - M.off[cq[q]]));
-        }
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const uint32_t u = b + (uint32_t)q * kTileThreads;
-            if (u < total) {
-                const int c = cq[q];
-                store(u, v[q], c % TL.uw, (c / TL.uw) % TL.uh, c / (TL.uw * TL.uh));
-            }
+    for (int q = 0; q < kStageQ; ++q) {
+        const uint32_t u = threadIdx.x + (uint32_t)q * kTileThreads;
+        if (u < total) {
+            const int c = cellof[u];
+            R.v[q] = load(M.gs[c] + (u - M.off[c]));
         }
     }
+}
+template <typename P, typename Store>
+__device__ __forceinline__ void tile_stage_store(const Tiles& TL, const TileMeta& M,
+                                                 const uint16_t* cellof, const StageRegs<P>& R,
+                                                 Store&& store) {
+    const uint32_t total = M.total;
+#pragma unroll
+    for (int q = 0; q < kStageQ; ++q) {
+        const uint32_t u = threadIdx.x + (uint32_t)q * kTileThreads;
+        if (u < total) {
+            const int c = cellof[u];
+            store(u, R.v[q], c % TL.uw, (c / TL.uw) % TL.uh, c / (TL.uw * TL.uh));
+        }
+    }
+}
+template <typename Load, typename Store>
+__device__ __forceinline__ void tile_stage(const Tiles& TL, TileMeta& M, uint16_t* cellof,
+                                           Load&& load, Store&& store) {
+    tile_cellof(TL, M, cellof);
+    using P = decltype(load(0u));
+    StageRegs<P> R;
+    tile_stage_loads(M, cellof, load, R);
+    tile_stage_store(TL, M, cellof, R, store);
 }
 
 // Union-frame record: cell-relative fixed point plus the union cell times 2^27.
@@ -309,10 +372,11 @@ __device__ __forceinline__ ListHead tile_list_head(const uint4* __restrict__ lis
 // scratch memory and wait on every fetch at the top of the loop).  Two
 // octets per iteration, for a longer fetch distance, measured slower (the
 // larger code and register count cost more than the latency they hide).
-template <typename Load, typename Body>
+template <int kGroup = 8, typename Load, typename Body>
 __device__ __forceinline__ void tile_list_loop(const uint4* __restrict__ list, uint32_t i,
                                                uint32_t cap, uint32_t cnt, const ListHead& head,
                                                Load&& load, Body&& body) {
+    static_assert(kGroup == 8 || kGroup == 4, "whole or half octets");
     using P = decltype(load(0u));
     const uint32_t nfull = cnt >> 3, rest = cnt & 7u;
     const uint32_t noct = nfull + (rest ? 1u : 0u);
@@ -326,11 +390,14 @@ __device__ __forceinline__ void tile_list_loop(const uint4* __restrict__ list, u
         const uint4 cur = nxt;
         nxt = nxt2;
         nxt2 = base[(size_t)min(k8 + 2, last) * 64];
-        P p[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) p[e] = load(half_of(cur, e));
+        for (int h = 0; h < 8; h += kGroup) {
+            P p[kGroup];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) body(p[e]);
+            for (int e = 0; e < kGroup; ++e) p[e] = load(half_of(cur, h + e));
+#pragma unroll
+            for (int e = 0; e < kGroup; ++e) body(p[e]);
+        }
     }
     if (rest) {
 #pragma unroll
@@ -583,6 +650,20 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_density(
 // complete, over the union's position, velocity and (rho, P) records staged
 // in LDS, with momentum_close as the epilogue; per-tile partial sums of the
 // diagnostics into diag_part[q * stride + tile].
+//
+// The staging takes most of the LDS, so one workgroup runs per CU and
+// nothing else covers its global round trips (a tile's cell ranges, then
+// its records, then its targets' counts and list heads: about 45% of the
+// pass measured without the pair loops).  Each workgroup therefore takes
+// every P-th tile (P workgroups, one per CU, so that the tiles in flight
+// are P consecutive ones) and issues, with the loads of its tile t's
+// targets, the staging loads of its next tile (whose cell ranges were set
+// up before) and the cell-range loads of the one after: the three round
+// trips overlap.  (They cannot reach past the first wait of the pair loops:
+// the vector memory counter is in order.)  After the pair loops the loaded
+// records and ranges go to the LDS that tile t no longer needs; two tile
+// metas and two cell tables alternate.  The pair loops take half octets at
+// a time, which keeps the staging registers clear of spills.
 template <int S, int KERNEL>
 __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
     int n, Grid G, PairConst<float> C, Tiles TL, int cap_union, const int4* __restrict__ pos,
@@ -592,75 +673,136 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_momentum(
     const uint32_t* __restrict__ ncnt, State St, int kick, int drift, double hdt, double dt,
     uint32_t* __restrict__ key, uint32_t* __restrict__ counts, uint32_t* __restrict__ flags,
     double* __restrict__ diag_part, int stride) {
-    __shared__ TileMeta M;
+    __shared__ TileMeta MM[2];
+    __shared__ uint16_t cellofs[2][kTileCap];
     __shared__ int4 Pi[kTileCap];
     __shared__ float4 V[kTileCap];
     __shared__ float2 RP[kTileCap];
-    __shared__ uint16_t cellof[kTileCap];
-    const int blk = xcd_block();
+    // tiles w, w + P, w + 2P, ... (P workgroups): the tiles in flight at
+    // any time are P consecutive ones, each XCD's a contiguous run of them
+    const int P = (int)gridDim.x;
+    const int t0 = xcd_block();
+    const int t1 = TL.ntiles;
+    if (t0 >= t1) return;  // the whole workgroup
+    struct Rc {
+        int4 p;
+        float4 v;
+        float2 rp;
+    };
+    auto load_rc = [&](uint32_t j) { return Rc{pos[j], vel[j], rp[j]}; };
+    auto store_rc = [&](uint32_t u, const Rc& r, int ux, int uy, int uz) {
+        Pi[u] = tile_rec(r.p, ux, uy, uz);
+        V[u] = r.v;
+        RP[u] = r.rp;
+    };
+    auto fits = [&](const TileMeta& M) { return M.total <= (uint32_t)cap_union; };
     int c0[3];
-    tile_origin(TL, blk, c0);
-    double dsum[4] = {0.0, 0.0, 0.0, 0.0};
-    if (tile_empty(G, TL, c0, cstart, cend)) {
-        if (diag_part) tile_block_sum<4>(dsum, diag_part, blk, stride);
-        return;
+    // prologue: tile t0 set up and staged, tile t0 + 1 set up
+    tile_origin(TL, t0, c0);
+    tile_setup(G, TL, c0, cstart, cend, n, MM[0]);
+    tile_cellof(TL, MM[0], cellofs[0]);
+    if (fits(MM[0])) {
+        StageRegs<Rc> R0;
+        tile_stage_loads(MM[0], cellofs[0], load_rc, R0);
+        tile_stage_store(TL, MM[0], cellofs[0], R0, store_rc);
     }
-    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
-    const bool fits = total <= (uint32_t)cap_union;
-    if (fits) {
-        struct Rc {
-            int4 p;
-            float4 v;
-            float2 rp;
-        };
-        tile_stage(TL, M, cellof, [&](uint32_t j) { return Rc{pos[j], vel[j], rp[j]}; },
-                   [&](uint32_t u, const Rc& r, int ux, int uy, int uz) {
-                       Pi[u] = tile_rec(r.p, ux, uy, uz);
-                       V[u] = r.v;
-                       RP[u] = r.rp;
-                   });
+    if (t0 + P < t1) {
+        tile_origin(TL, t0 + P, c0);
+        tile_setup(G, TL, c0, cstart, cend, n, MM[1]);  // its barriers also publish the staging
+        tile_cellof(TL, MM[1], cellofs[1]);
+    } else {
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < M.ntargets; t += kTileThreads) {
-            uint32_t ui, i;
-            int uc[3];
-            tile_target(TL, M, t, &ui, &i, uc);
-            // every global load of the target up front: count, type, the
-            // list's first octets and the epilogue's state
-            const uint32_t cnt = ncnt[i];
-            const bool fluid = type[i] == 0;
-            const ListHead head = tile_list_head(list, i, cap);
-            const CloseIn ci = close_load<3>((int)i, St, drift, diag_part != nullptr);
-            if (cnt > cap) continue;  // the fallback's
-            float acc[3] = {0.f, 0.f, 0.f};
-            if (fluid) {
-                const int4 pi = Pi[ui];
-                const float4 vi = V[ui];
-                const float2 rpi = RP[ui];
-                float ax = C.g[0], ay = C.g[1], az = C.g[2];
-                struct Nb {
-                    int4 p;
-                    float4 v;
-                    float2 rp;
-                };
-                tile_list_loop(list, i, cap, cnt, head,
-                               [&](uint32_t u) { return Nb{Pi[u], V[u], RP[u]}; },
-                               [&](const Nb& b) {
-                                   const Geom<float> g =
-                                       pair_geom<3>(pi, b.p, 0, 0, 0, 0, 0, 0, C);
-                                   momentum_add<3, KERNEL, float>(ax, ay, az, g, rec_mass(b.p),
-                                                                  vi, rpi, b.v, b.rp, C);
-                               });
-                acc[0] = ax;
-                acc[1] = ay;
-                acc[2] = az;
-            }
-            double dv[4] = {0.0, 0.0, 0.0, 0.0};
-            momentum_close<3, float>((int)i, acc, fluid, St, G, kick, drift, hdt, dt, key, counts,
-                                     flags, diag_part != nullptr, dv, &ci);
-            for (int q = 0; q < 4; ++q) dsum[q] += dv[q];
-        }
     }
-    if (diag_part) tile_block_sum<4>(dsum, diag_part, blk, stride);
+    int cur = 0;
+    for (int t = t0; t < t1; t += P) {
+        const TileMeta& M = MM[cur];
+        const TileMeta& MN = MM[cur ^ 1];
+        // issued with the targets' loads: the next tile's staging loads and
+        // the cell-range loads of the one after
+        const bool stage_next = t + P < t1 && fits(MN);
+        StageRegs<Rc> R;
+        if (stage_next) tile_stage_loads(MN, cellofs[cur ^ 1], load_rc, R);
+        const bool setup_next2 = t + 2 * P < t1;
+        int c2[3] = {0, 0, 0};
+        SetupLoads sl{};
+        if (setup_next2) {
+            tile_origin(TL, t + 2 * P, c2);
+            sl = tile_setup_loads(G, TL, c2, cstart, cend);
+        }
+        double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+        const uint32_t nt = M.ntargets;
+        if (fits(M) && nt > 0) {
+            // every global load of a target up front (count, type, the list's
+            // first octets, the epilogue's state); those of a thread's next
+            // target while it works on the current one
+            struct Tgt {
+                uint32_t ui, i, cnt;
+                bool fluid;
+                ListHead head;
+                CloseIn ci;
+            };
+            auto target_loads = [&](uint32_t tt) {
+                Tgt g;
+                int uc[3];
+                tile_target(TL, M, tt, &g.ui, &g.i, uc);
+                g.cnt = ncnt[g.i];
+                g.fluid = type[g.i] == 0;
+                g.head = tile_list_head(list, g.i, cap);
+                g.ci = close_load<3>((int)g.i, St, drift, diag_part != nullptr);
+                return g;
+            };
+            for (uint32_t tt = threadIdx.x; tt < nt; tt += kTileThreads) {
+                const Tgt cur_t = target_loads(tt);
+                const uint32_t ui = cur_t.ui, i = cur_t.i, cnt = cur_t.cnt;
+                if (cnt > cap) continue;  // the fallback's
+                float acc[3] = {0.f, 0.f, 0.f};
+                if (cur_t.fluid) {
+                    const int4 pi = Pi[ui];
+                    const float4 vi = V[ui];
+                    const float2 rpi = RP[ui];
+                    float ax = C.g[0], ay = C.g[1], az = C.g[2];
+                    struct Nb {
+                        int4 p;
+                        float4 v;
+                        float2 rp;
+                    };
+                    tile_list_loop<4>(list, i, cap, cnt, cur_t.head,
+                                   [&](uint32_t u) { return Nb{Pi[u], V[u], RP[u]}; },
+                                   [&](const Nb& b) {
+                                       const Geom<float> g =
+                                           pair_geom<3>(pi, b.p, 0, 0, 0, 0, 0, 0, C);
+                                       momentum_add<3, KERNEL, float>(ax, ay, az, g,
+                                                                      rec_mass(b.p), vi, rpi,
+                                                                      b.v, b.rp, C);
+                                   });
+                    acc[0] = ax;
+                    acc[1] = ay;
+                    acc[2] = az;
+                }
+                double dv[4] = {0.0, 0.0, 0.0, 0.0};
+                momentum_close<3, float>((int)i, acc, cur_t.fluid, St, G, kick, drift, hdt, dt,
+                                         key, counts, flags, diag_part != nullptr, dv,
+                                         &cur_t.ci);
+                for (int q = 0; q < 4; ++q) dsum[q] += dv[q];
+            }
+        }
+        if (diag_part) tile_block_sum<4>(dsum, diag_part, t, stride);
+        __syncthreads();  // tile t's records, meta and cell table are free
+        if (stage_next) {
+#pragma unroll
+            for (int q = 0; q < kStageQ; ++q) keep_in_flight(R.v[q]);
+            tile_stage_store(TL, MN, cellofs[cur ^ 1], R, store_rc);
+        }
+        if (setup_next2) {
+            keep_in_flight(sl.s);
+            keep_in_flight(sl.e);
+            tile_setup_finish(G, TL, c2, n, sl, MM[cur]);
+            tile_cellof(TL, MM[cur], cellofs[cur]);  // its barrier publishes the staging
+        } else {
+            __syncthreads();
+        }
+        cur ^= 1;
+    }
 }
 
 // Fallback density: the targets the tile build left (count above cap, or
