@@ -302,6 +302,8 @@ inline sph::Tiles make_tiles(const sph_params* p, const sph::Grid& G, int64_t n,
         T.csf[k] = (float)G.cs[k];
         T.inv_csf[k] = (float)(1.0 / G.cs[k]);
     }
+    T.inv_uw = 1.0f / (float)T.uw;
+    T.inv_uwh = 1.0f / (float)(T.uw * T.uh);
     T.cen[0] = T.uw / 2;
     T.cen[1] = T.uh / 2;
     T.cen[2] = T.ud / 2;

@@ -59,7 +59,27 @@ struct Tiles {
     int cen[3];            // union centre in cells (uw/2, uh/2, ud/2): origin of the float copy
     float rclip2;          // R^2 (1 + 1e-4): rows farther than this hold no neighbour
     float clip_pad;        // 1e-4 of a cell: padding of a row's clipped x range
+    float inv_uw, inv_uwh; // 1 / uw, 1 / (uw uh): union cell coordinates (union_coords)
 };
+
+// q = floor(c / d) for 0 <= c < 2^10 and 1 <= d <= 144, inv_d = fl(1 / d):
+// (c + 1/2) / d is at least 1/(2d) >= 1/288 away from an integer, and the
+// FP32 product (c + 1/2) inv_d is within 2^-12 of it, so its truncation is
+// exact (a few VALU instructions instead of an integer division).
+static_assert(kTileCellsMax <= 1024 && kTileUnionAxisMax * kTileUnionAxisMax <= 144,
+              "small_quot's range");
+__device__ __forceinline__ int small_quot(int c, float inv_d) {
+    return (int)(((float)c + 0.5f) * inv_d);
+}
+// Coordinates (ux, uy, uz) of union cell c of a tile.
+__device__ __forceinline__ void union_coords(const Tiles& TL, int c, int uc[3]) {
+    const int z = small_quot(c, TL.inv_uwh);
+    const int r = c - z * (TL.uw * TL.uh);
+    const int y = small_quot(r, TL.inv_uw);
+    uc[0] = r - y * TL.uw;
+    uc[1] = y;
+    uc[2] = z;
+}
 
 // Per-workgroup bookkeeping in LDS.
 struct TileMeta {
@@ -104,8 +124,10 @@ __device__ __forceinline__ int tile_axis(const Grid& G, int k, int c0, int u, in
     const int nc = G.nc[k];
     if (c >= 0 && c < nc) return c;
     if (!G.periodic[k]) return -1;
-    c %= nc;
-    return c < 0 ? c + nc : c;
+    // c lies within a few grid lengths: wrap by steps, not by a division
+    while (c < 0) c += nc;
+    while (c >= nc) c -= nc;
+    return c;
 }
 
 // Tile origin (first cell) of tile t.
@@ -165,10 +187,11 @@ __device__ __forceinline__ SetupLoads tile_setup_loads(const Grid& G, const Tile
         r.s[q] = r.e[q] = 0;
         r.in[q] = false;
         if (c < ncu) {
-            const int ux = c % TL.uw, uy = (c / TL.uw) % TL.uh, uz = c / (TL.uw * TL.uh);
-            const int gx = tile_axis(G, 0, c0[0], ux, TL.S);
-            const int gy = tile_axis(G, 1, c0[1], uy, TL.S);
-            const int gz = tile_axis(G, 2, c0[2], uz, TL.S);
+            int uc[3];
+            union_coords(TL, c, uc);
+            const int gx = tile_axis(G, 0, c0[0], uc[0], TL.S);
+            const int gy = tile_axis(G, 1, c0[1], uc[1], TL.S);
+            const int gz = tile_axis(G, 2, c0[2], uc[2], TL.S);
             if (gx >= 0 && gy >= 0 && gz >= 0) {
                 const int gc[3] = {gx, gy, gz};
                 const uint32_t key = cell_key(gc, G);
@@ -223,7 +246,11 @@ __device__ __forceinline__ uint32_t tile_setup_finish(const Grid& G, const Tiles
     uint32_t tcnt = 0;
     int tcell = 0;
     if (rr < ntc) {
-        const int x = rr % twc, y = (rr / twc) % thc, z = rr / (twc * thc);
+        // rr < kTileTargetCellsMax, twc thc <= 144: exact FP32 quotients
+        const int z = small_quot(rr, __builtin_amdgcn_rcpf((float)(twc * thc)));
+        const int rem = rr - z * (twc * thc);
+        const int y = small_quot(rem, __builtin_amdgcn_rcpf((float)twc));
+        const int x = rem - y * twc;
         tcell = (TL.S + x) + TL.uw * ((TL.S + y) + TL.uh * (TL.S + z));
         tcnt = M.off[tcell + 1] - M.off[tcell];
     }
@@ -261,9 +288,7 @@ __device__ __forceinline__ void tile_target(const Tiles& TL, const TileMeta& M, 
     const uint32_t k = t - M.tpre[lo];
     *ui = M.off[c] + k;
     *gi = M.gs[c] + k;
-    uc[0] = c % TL.uw;
-    uc[1] = (c / TL.uw) % TL.uh;
-    uc[2] = c / (TL.uw * TL.uh);
+    union_coords(TL, c, uc);
 }
 
 // Marks every target of the tile for the fallback (its union does not fit).
@@ -317,8 +342,9 @@ __device__ __forceinline__ void tile_stage_store(const Tiles& TL, const TileMeta
     for (int q = 0; q < kStageQ; ++q) {
         const uint32_t u = threadIdx.x + (uint32_t)q * kTileThreads;
         if (u < total) {
-            const int c = cellof[u];
-            store(u, R.v[q], c % TL.uw, (c / TL.uw) % TL.uh, c / (TL.uw * TL.uh));
+            int uc[3];
+            union_coords(TL, cellof[u], uc);
+            store(u, R.v[q], uc[0], uc[1], uc[2]);
         }
     }
 }
@@ -506,7 +532,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
     uint32_t counted = 0;
     bool need_fb = false;
     const float cxf = (float)TL.cen[0], cyf = (float)TL.cen[1], czf = (float)TL.cen[2];
-    const int ncu_w = TL.uw, ncu_wh = TL.uw * TL.uh;
     for (uint32_t t = threadIdx.x; t < M.ntargets; t += kTileThreads) {
         uint32_t ui, i;
         int uc[3];
@@ -524,8 +549,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
         // global memory, in the union frame)
         auto exact = [&](uint32_t u) {
             const int c = __float_as_int(Pf[u].w);
-            const int4 pj = tile_rec(pos[M.gs[c] + (u - M.off[c])], c % ncu_w,
-                                     (c / ncu_w) % TL.uh, c / ncu_wh);
+            int cu[3];
+            union_coords(TL, c, cu);
+            const int4 pj = tile_rec(pos[M.gs[c] + (u - M.off[c])], cu[0], cu[1], cu[2]);
             const Geom<float> g = pair_geom<3>(pi, pj, 0, 0, 0, 0, 0, 0, C);
             return geom_r2d(g, C) < C.R2_d;
         };
