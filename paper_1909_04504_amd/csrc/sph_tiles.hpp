@@ -499,11 +499,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
+    // the cell-range loads go out before the empty-box probe, so that the
+    // two round trips overlap
+    const SetupLoads sl = tile_setup_loads(G, TL, c0, cstart, cend);
     if (tile_empty(G, TL, c0, cstart, cend)) {
         if (count_pairs) tile_count(0u, pairs, blk);
         return;
     }
-    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
+    const uint32_t total = tile_setup_finish(G, TL, c0, n, sl, M);
     if (total > (uint32_t)cap_union) {
         tile_mark_overflow(M, ncnt);
         if (threadIdx.x == 0 && M.ntargets) *fallback = epoch;
@@ -646,8 +649,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_density(
     const int blk = xcd_block();
     int c0[3];
     tile_origin(TL, blk, c0);
+    const SetupLoads sl = tile_setup_loads(G, TL, c0, cstart, cend);
     if (tile_empty(G, TL, c0, cstart, cend)) return;
-    const uint32_t total = tile_setup(G, TL, c0, cstart, cend, n, M);
+    const uint32_t total = tile_setup_finish(G, TL, c0, n, sl, M);
     if (total > (uint32_t)cap_union) return;  // every target is the fallback's
     tile_stage(TL, M, cellof, [&](uint32_t j) { return pos[j]; },
                [&](uint32_t u, const int4& r, int ux, int uy, int uz) {
