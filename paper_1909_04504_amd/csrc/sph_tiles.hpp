@@ -559,68 +559,82 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_build(
             return geom_r2d(g, C) < C.R2_d;
         };
         uint32_t cnt = 0;
-        // the (2S+1)^2 stencil rows in walk order; a loop, not unrolled, so the
-        // kernel's code stays small enough for the instruction cache
+        // the (2S+1)^2 stencil rows in walk order (z planes, then y rows);
+        // loops, not unrolled, so the kernel's code stays small enough for the
+        // instruction cache.  A plane's distance is taken once for its rows,
+        // and the x range in cell units from px_c, the target's x in cells
+        // shifted by the union centre and 1/2 (the clip keeps its margins:
+        // roundings of these forms move it by far less than clip_pad)
         constexpr int NR = 2 * S + 1;
+        const float px_c = pf.x * TL.inv_csf[0] + (cxf + 0.5f);
 #pragma unroll 1
-        for (int row = 0; row < NR * NR; ++row) {
-            const int uy = uc[1] + row % NR - S, uz = uc[2] + row / NR - S;
-            const float dz = fmaxf(fabsf(pf.z - ((float)uz - czf) * TL.csf[2]) - 0.5f * TL.csf[2], 0.f);
-            const float dy = fmaxf(fabsf(pf.y - ((float)uy - cyf) * TL.csf[1]) - 0.5f * TL.csf[1], 0.f);
-            const float w2 = TL.rclip2 - dy * dy - dz * dz;
-            if (clip && !(w2 > 0.f)) continue;
-            int xa = uc[0] - S, xb = uc[0] + S;
-            if (clip) {
-                const float w = __builtin_amdgcn_sqrtf(w2) + TL.clip_pad;
-                xa = max(xa, (int)floorf((pf.x - w) * TL.inv_csf[0] + cxf + 0.5f));
-                xb = min(xb, (int)floorf((pf.x + w) * TL.inv_csf[0] + cxf + 0.5f));
-                if (xa > xb) continue;
-            }
-            const int rowc = TL.uw * (uy + TL.uh * uz);
-            const uint32_t ua = M.off[rowc + xa], ue = M.off[rowc + xb + 1];
-            // candidates four at a time, the next four loaded while these
-            // are tested; those past the row's end (read from the padding or
-            // the next row) are infinitely far
-            uint32_t u = ua;
-            float4 c[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) c[q] = Pf[u + q];
+        for (int iz = 0; iz < NR; ++iz) {
+            const int uz = uc[2] + iz - S;
+            const float dz =
+                fmaxf(fabsf(pf.z - ((float)uz - czf) * TL.csf[2]) - 0.5f * TL.csf[2], 0.f);
+            const float w2z = TL.rclip2 - dz * dz;
+            if (clip && !(w2z > 0.f)) continue;
+            const int planec = TL.uw * TL.uh * uz;
 #pragma unroll 1
-            for (; u < ue; u += 4) {
-                const uint32_t lim = ue - u;  // candidates left in the row
-                float r2[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float dx = pf.x - c[q].x, ddy = pf.y - c[q].y, ddz = pf.z - c[q].z;
-                    r2[q] = dx * dx + ddy * ddy + ddz * ddz;
+            for (int iy = 0; iy < NR; ++iy) {
+                const int uy = uc[1] + iy - S;
+                const float dy =
+                    fmaxf(fabsf(pf.y - ((float)uy - cyf) * TL.csf[1]) - 0.5f * TL.csf[1], 0.f);
+                const float w2 = w2z - dy * dy;
+                if (clip && !(w2 > 0.f)) continue;
+                int xa = uc[0] - S, xb = uc[0] + S;
+                if (clip) {
+                    const float wc = (__builtin_amdgcn_sqrtf(w2) + TL.clip_pad) * TL.inv_csf[0];
+                    xa = max(xa, (int)floorf(px_c - wc));
+                    xb = min(xb, (int)floorf(px_c + wc));
+                    if (xa > xb) continue;
                 }
+                const int rowc = planec + TL.uw * uy;
+                const uint32_t ua = M.off[rowc + xa], ue = M.off[rowc + xb + 1];
+                // candidates four at a time, the next four loaded while these
+                // are tested; those past the row's end (read from the padding or
+                // the next row) are infinitely far
+                uint32_t u = ua;
+                float4 c[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) c[q] = Pf[u + 4 + q];
-                uint32_t acc[4];
-                bool band[4];
-                bool anyband = false;
+                for (int q = 0; q < 4; ++q) c[q] = Pf[u + q];
+#pragma unroll 1
+                for (; u < ue; u += 4) {
+                    const uint32_t lim = ue - u;  // candidates left in the row
+                    float r2[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float x = (uint32_t)q < lim ? r2[q] : __builtin_huge_valf();
-                    acc[q] = x < C.R2_lo ? 1u : 0u;
-                    band[q] = fabsf(x - C.R2_mid) < C.R2_w;
-                    anyband |= band[q];
-                }
-                if (__builtin_amdgcn_ballot_w64(anyband)) {
+                    for (int q = 0; q < 4; ++q) {
+                        const float dx = pf.x - c[q].x, ddy = pf.y - c[q].y, ddz = pf.z - c[q].z;
+                        r2[q] = dx * dx + ddy * ddy + ddz * ddz;
+                    }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (band[q]) acc[q] = exact(u + q) ? 1u : 0u;
-                }
-                const uint32_t c_in = cnt;
+                    for (int q = 0; q < 4; ++q) c[q] = Pf[u + 4 + q];
+                    uint32_t acc[4];
+                    bool band[4];
+                    bool anyband = false;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    my[cnt & 15] = (uint16_t)(u + q);
-                    cnt += acc[q];
-                }
-                // an octet completed (at most one per group of four)
-                if ((cnt ^ c_in) & ~7u) {
-                    const uint32_t k8 = c_in >> 3;
-                    if (k8 < (cap >> 3)) list[tile_octet(i, cap, k8)] = ring_octet(k8);
+                    for (int q = 0; q < 4; ++q) {
+                        const float x = (uint32_t)q < lim ? r2[q] : __builtin_huge_valf();
+                        acc[q] = x < C.R2_lo ? 1u : 0u;
+                        band[q] = fabsf(x - C.R2_mid) < C.R2_w;
+                        anyband |= band[q];
+                    }
+                    if (__builtin_amdgcn_ballot_w64(anyband)) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (band[q]) acc[q] = exact(u + q) ? 1u : 0u;
+                    }
+                    const uint32_t c_in = cnt;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        my[cnt & 15] = (uint16_t)(u + q);
+                        cnt += acc[q];
+                    }
+                    // an octet completed (at most one per group of four)
+                    if ((cnt ^ c_in) & ~7u) {
+                        const uint32_t k8 = c_in >> 3;
+                        if (k8 < (cap >> 3)) list[tile_octet(i, cap, k8)] = ring_octet(k8);
+                    }
                 }
             }
         }
